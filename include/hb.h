@@ -1,0 +1,206 @@
+/*
+ * libhb -- MI355X (gfx950) RK4 solver for the Higgs boson equation in de
+ * Sitter spacetime (Balogh, Banda, Yagdjian, arXiv:1803.01291).
+ *
+ * The library advances the first-order system of section 2.1, eq. (rhs),
+ *
+ *     phi_t = psi
+ *     psi_t = -3 psi + inv_L2 exp(-2t) Lap_h phi + mu2 phi - lambda phi^3
+ *
+ * (eq. (higgs-boson-rescalled) with inv_L2 = 1/L^2; inv_L2 = 1 is eq. (HBE)
+ * itself) with the classical explicit fourth-order Runge-Kutta method of
+ * section 2.1 and the fourth-order central-difference Laplacian of section 2.1
+ * (13-point star), on a uniform 3-D grid with the zero boundary condition of
+ * eq. (BC) realised as a 2-cell zero halo.
+ *
+ * Grid: an axis with n points on [lo, hi] has h = (hi - lo)/n and cell-centred
+ * nodes x_i = lo + (i + 1/2) h.  Host/device arrays exchanged through this API
+ * hold interior points only, C-ordered [nz][ny][nx] (x fastest), contiguous.
+ *
+ * Conventions for every call:
+ *  - Functions return HB_OK (0) or a negative HB_E_* code; no exception
+ *    crosses the ABI.  hb_last_error() gives a message for the calling thread.
+ *  - Pointers marked "device" are HIP device pointers on the current device;
+ *    "host" pointers are ordinary host memory.  The caller keeps ownership of
+ *    every array it passes; the library copies what it needs before returning
+ *    (host) or in stream order (device).
+ *  - Handles are not thread-safe; distinct handles may be used concurrently.
+ *  - All device work of a handle is ordered on its stream (hb_config.stream,
+ *    or a stream the library creates when that is NULL).
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HB_OK 0
+#define HB_E_ARG (-1)       /* invalid argument                                   */
+#define HB_E_CFL (-2)       /* dt beyond the RK4 linear stability limit           */
+#define HB_E_NOMEM (-3)     /* device or host allocation failed                   */
+#define HB_E_HIP (-4)       /* HIP runtime error                                  */
+#define HB_E_STATE (-5)     /* call out of order (e.g. step before initial data)  */
+#define HB_E_BUSY (-6)      /* pool: no free slot or HBM budget exhausted         */
+#define HB_E_NONFINITE (-7) /* diagnostics found NaN/Inf in the state             */
+
+/* hb_config.precision */
+#define HB_F64 0  /* FP64 storage and arithmetic                                */
+#define HB_F32C 1 /* FP32 field storage and stencil; the RK4 state update is    */
+                  /* carried in FP64 registers and stored as FP32 hi + lo       */
+
+/* memory kind of a user array */
+#define HB_HOST 0
+#define HB_DEVICE 1
+
+/* element type of a user array */
+#define HB_DTYPE_F64 0
+#define HB_DTYPE_F32 1
+
+/* hb_config.flags */
+#define HB_ALLOW_UNSTABLE 1u /* skip the dt stability check                    */
+#define HB_USE_GRAPH 2u      /* replay captured hipGraphs of several steps     */
+
+typedef struct hb_config {
+    int32_t n[3];        /* interior points along x, y, z (each >= 1)              */
+    double lo[3], hi[3]; /* box [lo_d, hi_d] per axis, hi_d > lo_d                  */
+    double mu2;          /* mu^2 of eq. (HBE) (any finite real)                     */
+    double lambda;       /* lambda of eq. (HBE) (any finite real; < 0 allowed)      */
+    double inv_L2;       /* 1/L^2 of eq. (higgs-boson-rescalled); 1 for eq. (HBE)   */
+    double t0;           /* initial time                                            */
+    double dt;           /* RK4 time step (> 0)                                     */
+    int32_t precision;   /* HB_F64 or HB_F32C                                       */
+    uint32_t flags;      /* HB_ALLOW_UNSTABLE | HB_USE_GRAPH                        */
+    void* stream;        /* hipStream_t to order work on, or NULL                   */
+} hb_config;
+
+/* FP64 diagnostics of the current state (t = t0 + step dt), cell volume
+ * dV = hx hy hz:
+ *   integral = dV sum phi, l2_phi = sqrt(dV sum phi^2), l2_psi likewise,
+ *   linf_phi = max|phi|, linf_psi = max|psi|,
+ *   lap_max  = c(t) max|Lap_h phi|            (the paper's P(t), Example 4)
+ *   energy   = dV sum [psi^2/2 + c(t) phi (-Lap_h phi)/2 - mu2 phi^2/2 + lambda phi^4/4]
+ *   nonfinite = number of NaN/Inf values of phi and psi,
+ *   negative  = number of interior points with phi < 0 (sign changes: the
+ *               paper's bubbles, section 1). */
+typedef struct hb_diag {
+    double t;
+    int64_t step;
+    double integral, l2_phi, l2_psi, linf_phi, linf_psi, lap_max, energy;
+    int64_t nonfinite, negative;
+} hb_diag;
+
+typedef struct hb_solver hb_solver;
+typedef struct hb_batch hb_batch;
+typedef struct hb_pool hb_pool;
+
+/* ---- single solve (section 2.1) ------------------------------------------ */
+
+/* Validate cfg, allocate all device state (library-owned) and zero the halo.
+ * The stability check requires dt * sqrt(c0 * sum_d 16/(3 h_d^2)) <= 2 sqrt(2),
+ * c0 = inv_L2 exp(-2 t0) (RK4's imaginary-axis limit against the largest
+ * eigenvalue of -Lap_h); HB_E_CFL otherwise unless HB_ALLOW_UNSTABLE.
+ * Errors: HB_E_ARG, HB_E_CFL, HB_E_NOMEM, HB_E_HIP.  *out is NULL on error. */
+int hb_create(const hb_config* cfg, hb_solver** out);
+
+/* Set phi(., t0) = phi0 and phi_t(., t0) = phi1 (eq. (HBEinit)); resets the
+ * step counter to 0.  phi0/phi1: nz*ny*nx values of `dtype` in `mem`
+ * (phi1 may be NULL for zero).  For HB_F32C an FP64 input is split into an
+ * FP32 high part and an FP32 low part.  Host inputs are copied before the call
+ * returns; device inputs are read in stream order. */
+int hb_set_initial(hb_solver* s, const void* phi0, const void* phi1, int mem, int dtype);
+
+/* Restore a checkpoint: state (phi, psi) at step n (t = t0 + n dt). */
+int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int mem, int dtype);
+
+/* Enqueue nsteps RK4 steps (4 fused stage kernels each) on the solver's stream
+ * and return without waiting.  HB_E_STATE before initial data. */
+int hb_step(hb_solver* s, int64_t nsteps);
+
+/* Like hb_step, but waits after every step and returns the summed device time
+ * of each of the 4 stage kernels in stage_ms[0..3] (HIP events on the
+ * solver's stream around each launch).  For measurement. */
+int hb_step_timed(hb_solver* s, int64_t nsteps, double* stage_ms);
+
+/* Wait for the solver's stream, then copy the interior state out.  Either
+ * output may be NULL.  For HB_F32C the value returned is hi + lo in FP64. */
+int hb_read(hb_solver* s, void* phi, void* phi_t, int mem, int dtype);
+
+/* Current time and step count (host bookkeeping; no wait). */
+int hb_time(const hb_solver* s, double* t, int64_t* n);
+
+/* Wait for all work enqueued on the solver's stream. */
+int hb_sync(hb_solver* s);
+
+/* FP64 diagnostics (deterministic fixed-order reductions); waits.  Returns
+ * HB_E_NONFINITE (with *out filled) when the state holds NaN/Inf. */
+int hb_diagnostics(hb_solver* s, hb_diag* out);
+
+/* Tile shape of the stage kernels: by in {8, 16} rows of 64 columns, zc >= 1
+ * planes per tile (0 = library default).  Results do not depend on it. */
+int hb_set_tiling(hb_solver* s, int by, int zc);
+
+/* Time every candidate tile shape for `trial_steps` steps on the current
+ * state, keep the fastest, and restore the state (bitwise).  The choice is
+ * cached per (device, precision, grid) in the JSON file named by the
+ * HB_TUNE_CACHE environment variable, if set. */
+int hb_autotune(hb_solver* s, int trial_steps, int* by, int* zc);
+
+/* Free everything (NULL-safe). */
+int hb_destroy(hb_solver* s);
+
+/* Device bytes hb_create would allocate for cfg (0 on invalid cfg). */
+size_t hb_footprint(const hb_config* cfg);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* hb_last_error(void);
+
+/* ---- batched form: many independent solves, one launch per RK4 stage ------ */
+
+/* count solves with their own grid, coefficients, dt and precision.  All
+ * solves of one precision advance together in one launch per stage over a
+ * device tile table spanning them.  Results are bitwise equal to hb_step on
+ * the same solve.  stream: hipStream_t or NULL. */
+int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** out);
+int hb_batch_set_initial(hb_batch* b, int i, const void* phi0, const void* phi1, int mem, int dtype);
+int hb_batch_step(hb_batch* b, int64_t nsteps);
+int hb_batch_read(hb_batch* b, int i, void* phi, void* phi_t, int mem, int dtype);
+int hb_batch_sync(hb_batch* b);
+int hb_batch_set_tiling(hb_batch* b, int by, int zc);
+int hb_batch_destroy(hb_batch* b);
+
+/* ---- served form: continuous batching of admitted solves ------------------ */
+
+/* A pool with an HBM budget (bytes) and at most max_slots resident solves. */
+int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out);
+
+/* Admit one solve of `steps` steps with initial data (as hb_set_initial).
+ * Returns HB_E_BUSY (nothing allocated, nothing changed) when no slot is free
+ * or hb_footprint(cfg) exceeds the unused budget.  The solve joins the active
+ * set at the next hb_pool_advance. */
+int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void* phi1, int mem,
+                  int dtype, int64_t steps, int* slot);
+
+/* Advance every active solve by up to k steps (each stops at its own step
+ * count); one launch per stage per precision over all of them. */
+int hb_pool_advance(hb_pool* p, int k);
+
+/* Slots that finished since the last poll (up to cap); *ndone is the count. */
+int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone);
+
+/* Number of admitted, unfinished solves and bytes of the budget in use. */
+int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use);
+
+int hb_pool_read(hb_pool* p, int slot, void* phi, void* phi_t, int mem, int dtype);
+int hb_pool_release(hb_pool* p, int slot);
+int hb_pool_destroy(hb_pool* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

@@ -1,0 +1,70 @@
+// Internal layouts shared by the HIP kernels and the host runtime of libhb.
+//
+// Field layout in HBM (one allocation per solve, all fields alike):
+//   element (x, y, z), x in [-2, nx+2), y in [-2, ny+2), z in [-2, nz+2),
+//   lives at origin + z*sz + y*sy + x, where origin is the interior point
+//   (0, 0, 0).  The row pitch sy is nx+4 rounded up to a 128-byte multiple and
+//   origin sits on a 128-byte boundary, so every interior row starts aligned;
+//   the 2-cell halo (the zero boundary condition) is zeroed once at creation
+//   and never written afterwards.
+#pragma once
+
+#include <stdint.h>
+
+namespace hb {
+
+// precision of a solve
+enum : int { PREC_F64 = 0, PREC_F32C = 1 };
+
+// One solve as the stage kernels see it (device resident, 128-byte aligned).
+struct SolveDesc {
+    void* y_phi[2];      // state phi (FP64) or its FP32 high part, ping-pong by step parity
+    void* y_psi[2];      // state psi, same
+    void* g[3];          // psi-forcing of stages 1..3 (G1, G2, G3)
+    float* lo_phi;       // FP32c: low parts of the compensated state (updated in place)
+    float* lo_psi;
+    const double* ctab;  // c(t) per stage: ctab[4 n + s], s = 0..3
+    long long sy, sz;    // row and plane pitch in elements
+    int nx, ny, nz, prec;
+    double w0;           // -5/2 (1/hx^2 + 1/hy^2 + 1/hz^2)
+    double w1[3];        // 4/3 / h_d^2
+    double w2[3];        // -1/12 / h_d^2
+    double mu2, lambda, dt, hdt, dt6;
+    long long nstep;     // steps completed (advanced by the tick kernel)
+    long long target;    // stepping stops when nstep reaches target
+    long long pad_[2];
+};
+
+// One block of work: an x-y tile of 64 x BY columns over z in [z0, z1).
+struct Tile {
+    int solve;  // index into the launch group's descriptor array
+    int x0, y0, z0, z1;
+    int pad_[3];
+};
+
+constexpr int TILE_X = 64;
+
+// Launchers (implemented in hb_kernels.hip).  All are asynchronous on `stream`.
+int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile* tiles,
+                 int ntiles, long long kstep, void* stream);
+int launch_tick(SolveDesc* descs, int count, long long k, void* stream);
+int launch_set_target(SolveDesc* descs, int index, long long target, void* stream);
+int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream);
+
+// Contiguous user array [nz][ny][nx] of src_dtype (0 = f64, 1 = f32) into a
+// pitched field.  FP64 fields take the value; FP32c fields take
+// hi = (float)v and lo = (float)(v - hi).  `src` may be NULL for zeros.
+int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,
+                  long long sz, void* hi, float* lo, void* stream);
+// Pitched field into a contiguous user array of dst_dtype (FP32c: hi + lo in FP64).
+int launch_pack(int prec, int dst_dtype, void* dst, int nx, int ny, int nz, long long sy,
+                long long sz, const void* hi, const float* lo, void* stream);
+
+// Diagnostics: per-block partials then one fixed-order final pass (deterministic).
+enum { DIAG_SUM_PHI = 0, DIAG_SUM_PHI2, DIAG_SUM_PSI2, DIAG_MAX_PHI, DIAG_MAX_PSI, DIAG_MAX_LAP,
+       DIAG_ENERGY, DIAG_NONFINITE, DIAG_NEGATIVE, DIAG_COUNT };
+int diag_partials_needed(int nx, int ny, int nz);
+int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, double* partials,
+                       int nparts, double* out, void* stream);
+
+}  // namespace hb

@@ -1,0 +1,483 @@
+// HIP kernels for gfx950: one RK4 stage of the Higgs boson equation in de
+// Sitter spacetime per launch (Balogh, Banda, Yagdjian, section 2.1).
+//
+// System (eq. (rhs)):  phi_t = psi,
+//                      psi_t = -3 psi + c(t) Lap_h phi + mu2 phi - lambda phi^3,
+// with the fourth-order 13-point Laplacian of section 2.1 and classical RK4.
+//
+// Storage scheme ("G storage", 19 field passes per step).  Only the psi
+// component of each stage derivative needs storing, because the phi component
+// of k_s is the psi component of the stage-s input:
+//   G_s = g(t_s, S_phi,s, S_psi,s),  g(phi, psi) = -3 psi + c Lap phi + mu2 phi - lambda phi^3
+//   S_phi,1 = Y_phi                          S_psi,1 = Y_psi
+//   S_phi,2 = Y_phi + dt/2 Y_psi             S_psi,2 = Y_psi + dt/2 G1
+//   S_phi,3 = Y_phi + dt/2 S_psi,2           S_psi,3 = Y_psi + dt/2 G2
+//   S_phi,4 = Y_phi + dt   S_psi,3           S_psi,4 = Y_psi + dt   G3
+//   phi' = Y_phi + dt/6 (Y_psi + 2 S_psi,2 + 2 S_psi,3 + S_psi,4)
+//   psi' = Y_psi + dt/6 (G1 + 2 G2 + 2 G3 + G4)
+// which is the classical RK4 update with each stage input formed in the same
+// order as the textbook form.  Stage s reads, per point,
+//   s=1: Y_phi (stencil), Y_psi                        -> writes G1
+//   s=2: Y_phi, Y_psi (stencil), G1                     -> writes G2
+//   s=3: Y_phi, Y_psi, G1 (stencil), G2                 -> writes G3
+//   s=4: Y_phi, Y_psi, G2 (stencil), G1, G3             -> writes Y'_phi, Y'_psi
+// The state ping-pongs by step parity (stage 4 stencil-reads Y while writing Y').
+//
+// Kernel shape.  A block owns a 64 x BY column tile (64-wide = one wavefront
+// per row) and marches a z-range.  Each thread keeps its own column's stage
+// input S_phi at planes z-2..z+2 in registers (the z part of the star), and
+// the block stages plane z with a 2-cell x/y halo in LDS (the x and y parts).
+// The raw fields of the thread's own column are loaded three planes ahead and
+// those of the halo one plane ahead, so each plane's loads are in flight while
+// the previous plane computes.  One __syncthreads per plane (double-buffered
+// LDS).  No MFMA: the stencil is not a contraction and the path is bound by
+// HBM bandwidth.
+#include <hip/hip_runtime.h>
+
+#include "hb_internal.h"
+
+namespace hb {
+namespace {
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous range of the tile list, so tiles that share halo rows run on the
+// same XCD and meet in its L2.  Bijective on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n >> 3, r = n & 7;
+    const int x = b & 7, l = b >> 3;
+    return x * q + min(x, r) + l;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T* __restrict__ p, long long off, bool ok) {
+    return ok ? p[off] : T(0);
+}
+
+template <typename T, int STAGE, bool COMP>
+struct OwnRec {
+    T p, s, g1, g2, g3;
+    float lp, ls;
+};
+
+template <typename T, int STAGE, int BY, bool COMP>
+__global__ void __launch_bounds__(64 * BY)
+stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
+             long long kstep) {
+    constexpr int LX = TILE_X + 4;
+    constexpr int LY = BY + 4;
+    constexpr int NHALO = 4 * TILE_X + 4 * BY;
+    static_assert(NHALO <= 64 * BY, "one halo column per thread at most");
+    __shared__ T sm[2][LY][LX];
+
+    const Tile tl = tiles[xcd_remap(blockIdx.x, ntiles)];
+    const SolveDesc* __restrict__ d = descs + tl.solve;
+    const long long n = d->nstep + kstep;
+    if (n >= d->target) return;  // uniform over the block
+    const int par = (int)(n & 1);
+
+    const T* __restrict__ Yp = (const T*)d->y_phi[par];
+    const T* __restrict__ Ys = (const T*)d->y_psi[par];
+    const T* __restrict__ G1 = (const T*)d->g[0];
+    const T* __restrict__ G2 = (const T*)d->g[1];
+    const T* __restrict__ G3 = (const T*)d->g[2];
+    const long long sy = d->sy, sz = d->sz;
+    const int nx = d->nx, ny = d->ny;
+
+    const T c = (T)d->ctab[4 * n + (STAGE - 1)];
+    const T w0 = (T)d->w0;
+    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
+    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
+    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
+    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    const bool own_ld = (x < nx + 2) && (y < ny + 2);
+    const bool own_st = (x < nx) && (y < ny);
+    const long long own_off = (long long)y * sy + x;
+
+    // this thread's halo column, if any: 4 rows of 64 above/below the tile,
+    // then 2 columns left/right of each of the BY rows
+    bool has_halo = false, halo_ld = false;
+    int hlx = 0, hly = 0;
+    long long halo_off = 0;
+    if (tid < NHALO) {
+        int hx, hy;
+        if (tid < 4 * TILE_X) {
+            const int r = tid >> 6;
+            hy = (r < 2) ? tl.y0 - 2 + r : tl.y0 + BY + (r - 2);
+            hx = tl.x0 + (tid & 63);
+        } else {
+            const int h = tid - 4 * TILE_X;
+            const int k = h & 3;
+            hy = tl.y0 + (h >> 2);
+            hx = (k < 2) ? tl.x0 - 2 + k : tl.x0 + TILE_X + (k - 2);
+        }
+        has_halo = true;
+        halo_ld = (hx >= -2) && (hx < nx + 2) && (hy >= -2) && (hy < ny + 2);
+        hlx = hx - tl.x0 + 2;
+        hly = hy - tl.y0 + 2;
+        halo_off = (long long)hy * sy + hx;
+    }
+
+    using Rec = OwnRec<T, STAGE, COMP>;
+    auto load_own = [&](int z) {
+        Rec r;
+        const long long o = (long long)z * sz + own_off;
+        r.p = ldg(Yp, o, own_ld);
+        r.s = ldg(Ys, o, own_ld);
+        r.g1 = (STAGE >= 2) ? ldg(G1, o, own_ld) : T(0);
+        r.g2 = (STAGE >= 3) ? ldg(G2, o, own_ld) : T(0);
+        r.g3 = (STAGE == 4) ? ldg(G3, o, own_ld) : T(0);
+        if constexpr (COMP && STAGE == 4) {
+            r.lp = ldg(d->lo_phi, o, own_ld);
+            r.ls = ldg(d->lo_psi, o, own_ld);
+        } else {
+            r.lp = 0.f;
+            r.ls = 0.f;
+        }
+        return r;
+    };
+    // halo needs only the fields that make up the stencil input S_phi,s
+    struct HaloRec { T p, s, g; };
+    auto load_halo = [&](int z) {
+        HaloRec r;
+        const long long o = (long long)z * sz + halo_off;
+        const bool ok = has_halo && halo_ld;
+        r.p = ldg(Yp, o, ok);
+        r.s = (STAGE >= 2) ? ldg(Ys, o, ok) : T(0);
+        r.g = (STAGE == 3) ? ldg(G1, o, ok) : (STAGE == 4) ? ldg(G2, o, ok) : T(0);
+        return r;
+    };
+    auto formS = [&](T p, T s, T g) -> T {
+        if constexpr (STAGE == 1) return p;
+        if constexpr (STAGE == 2) return p + hdt * s;
+        if constexpr (STAGE == 3) return p + hdt * (s + hdt * g);
+        return p + dtT * (s + hdt * g);
+    };
+    auto formS_own = [&](const Rec& r) -> T {
+        return formS(r.p, r.s, (STAGE == 3) ? r.g1 : r.g2);
+    };
+
+    const int z0 = tl.z0, z1 = tl.z1;
+    Rec rm2 = load_own(z0 - 2), rm1 = load_own(z0 - 1);
+    Rec r0 = load_own(z0), r1 = load_own(z0 + 1), r2 = load_own(z0 + 2);
+    HaloRec h0 = load_halo(z0);
+    T q0 = formS_own(rm2), q1 = formS_own(rm1), q2 = formS_own(r0), q3 = formS_own(r1);
+    int buf = 0;
+
+    for (int z = z0; z < z1; ++z) {
+        Rec rn{};
+        HaloRec hn{};
+        if (z + 3 <= z1 + 1) rn = load_own(z + 3);
+        if (z + 1 < z1) hn = load_halo(z + 1);
+
+        const T q4 = formS_own(r2);
+        sm[buf][ty + 2][tx + 2] = q2;
+        if (has_halo) sm[buf][hly][hlx] = formS(h0.p, h0.s, h0.g);
+        __syncthreads();
+
+        const T(*P)[LX] = sm[buf];
+        const int lx = tx + 2, ly = ty + 2;
+        T lap = w0 * q2;
+        lap += w1x * (P[ly][lx - 1] + P[ly][lx + 1]);
+        lap += w2x * (P[ly][lx - 2] + P[ly][lx + 2]);
+        lap += w1y * (P[ly - 1][lx] + P[ly + 1][lx]);
+        lap += w2y * (P[ly - 2][lx] + P[ly + 2][lx]);
+        lap += w1z * (q1 + q3);
+        lap += w2z * (q0 + q4);
+
+        // centre: S_psi,s and the psi forcing g = -3 S_psi + c Lap + mu2 S - lambda S^3
+        T spsi;
+        if constexpr (STAGE == 1) spsi = r0.s;
+        if constexpr (STAGE == 2) spsi = r0.s + hdt * r0.g1;
+        if constexpr (STAGE == 3) spsi = r0.s + hdt * r0.g2;
+        if constexpr (STAGE == 4) spsi = r0.s + dtT * r0.g3;
+        const T S = q2;
+        const T g = -T(3) * spsi + c * lap + mu2 * S - lam * S * S * S;
+
+        const long long o = (long long)z * sz + own_off;
+        if (own_st) {
+            if constexpr (STAGE < 4) {
+                ((T*)d->g[STAGE - 1])[o] = g;
+            } else if constexpr (!COMP) {
+                const double dt6 = d->dt6;
+                const T k2 = r0.s + hdt * r0.g1;
+                const T k3 = r0.s + hdt * r0.g2;
+                ((T*)d->y_phi[par ^ 1])[o] = r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi);
+                ((T*)d->y_psi[par ^ 1])[o] =
+                    r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * r0.g3 + g);
+            } else {
+                // compensated state: v = hi + lo carried in FP64 registers;
+                // the stage derivatives come from the FP32 stage arithmetic
+                const double hd = d->hdt, dd = d->dt, dt6 = d->dt6;
+                const double p = (double)r0.p + (double)r0.lp;
+                const double s = (double)r0.s + (double)r0.ls;
+                const double a1 = r0.g1, a2 = r0.g2, a3 = r0.g3, a4 = g;
+                const double k2 = s + hd * a1, k3 = s + hd * a2, k4 = s + dd * a3;
+                const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
+                const double ns_ = s + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
+                const float hp = (float)np_, hs = (float)ns_;
+                ((float*)d->y_phi[par ^ 1])[o] = hp;
+                ((float*)d->y_psi[par ^ 1])[o] = hs;
+                d->lo_phi[o] = (float)(np_ - (double)hp);
+                d->lo_psi[o] = (float)(ns_ - (double)hs);
+            }
+        }
+        q0 = q1; q1 = q2; q2 = q3; q3 = q4;
+        r0 = r1; r1 = r2; r2 = rn;
+        h0 = hn;
+        buf ^= 1;
+    }
+}
+
+__global__ void tick_kernel(SolveDesc* descs, int count, long long k) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const long long v = descs[i].nstep + k;
+        descs[i].nstep = v < descs[i].target ? v : descs[i].target;
+    }
+}
+
+__global__ void set_target_kernel(SolveDesc* descs, int i, long long target) {
+    if (threadIdx.x == 0) descs[i].target = target;
+}
+
+__global__ void set_nstep_kernel(SolveDesc* descs, int i, long long nstep, long long target) {
+    if (threadIdx.x == 0) {
+        descs[i].nstep = nstep;
+        descs[i].target = target;
+    }
+}
+
+template <typename S, bool COMP>
+__global__ void unpack_kernel(const S* __restrict__ src, int nx, int ny, int nz, long long sy,
+                              long long sz, void* __restrict__ hi, float* __restrict__ lo) {
+    const long long total = (long long)nx * ny * nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int x = (int)(i % nx);
+        const long long r = i / nx;
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        const long long o = (long long)z * sz + (long long)y * sy + x;
+        const double v = src ? (double)src[i] : 0.0;
+        if constexpr (COMP) {
+            const float h = (float)v;
+            ((float*)hi)[o] = h;
+            lo[o] = (float)(v - (double)h);
+        } else {
+            ((double*)hi)[o] = v;
+        }
+    }
+}
+
+template <typename D, bool COMP>
+__global__ void pack_kernel(D* __restrict__ dst, int nx, int ny, int nz, long long sy, long long sz,
+                            const void* __restrict__ hi, const float* __restrict__ lo) {
+    const long long total = (long long)nx * ny * nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int x = (int)(i % nx);
+        const long long r = i / nx;
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        const long long o = (long long)z * sz + (long long)y * sy + x;
+        double v;
+        if constexpr (COMP) v = (double)((const float*)hi)[o] + (double)lo[o];
+        else v = ((const double*)hi)[o];
+        dst[i] = (D)v;
+    }
+}
+
+// ---- diagnostics (FP64, deterministic) ----------------------------------------
+
+constexpr int DIAG_THREADS = 256;
+
+template <bool COMP>
+__device__ __forceinline__ double fld(const void* hi, const float* lo, long long o) {
+    if constexpr (COMP) return (double)((const float*)hi)[o] + (double)lo[o];
+    return ((const double*)hi)[o];
+}
+
+// One block per (y, z) row group; per-thread partial sums in a fixed order,
+// then a fixed LDS tree.  Partials: DIAG_COUNT doubles per block.
+template <bool COMP>
+__global__ void __launch_bounds__(DIAG_THREADS)
+diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restrict__ partials) {
+    const int nx = d->nx, ny = d->ny, nz = d->nz;
+    const long long sy = d->sy, sz = d->sz;
+    const void* P = d->y_phi[par];
+    const void* S = d->y_psi[par];
+    const float* LP = d->lo_phi;
+    const float* LS = d->lo_psi;
+    const double w0 = d->w0, mu2 = d->mu2, lam = d->lambda;
+    double acc[DIAG_COUNT];
+    for (int k = 0; k < DIAG_COUNT; ++k) acc[k] = 0.0;
+    const long long rows = (long long)ny * nz;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int y = (int)(row % ny), z = (int)(row / ny);
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+            const long long o = (long long)z * sz + (long long)y * sy + x;
+            const double p = fld<COMP>(P, LP, o);
+            const double s = fld<COMP>(S, LS, o);
+            double lap = w0 * p;
+            const long long st[3] = {1, sy, sz};
+            for (int a = 0; a < 3; ++a) {
+                lap += d->w1[a] * (fld<COMP>(P, LP, o - st[a]) + fld<COMP>(P, LP, o + st[a]));
+                lap += d->w2[a] * (fld<COMP>(P, LP, o - 2 * st[a]) + fld<COMP>(P, LP, o + 2 * st[a]));
+            }
+            acc[DIAG_SUM_PHI] += p;
+            acc[DIAG_SUM_PHI2] += p * p;
+            acc[DIAG_SUM_PSI2] += s * s;
+            acc[DIAG_MAX_PHI] = fmax(acc[DIAG_MAX_PHI], fabs(p));
+            acc[DIAG_MAX_PSI] = fmax(acc[DIAG_MAX_PSI], fabs(s));
+            acc[DIAG_MAX_LAP] = fmax(acc[DIAG_MAX_LAP], fabs(lap));
+            acc[DIAG_ENERGY] += 0.5 * s * s + 0.5 * c * p * (-lap) - 0.5 * mu2 * p * p +
+                                0.25 * lam * p * p * p * p;
+            acc[DIAG_NONFINITE] += (isfinite(p) ? 0.0 : 1.0) + (isfinite(s) ? 0.0 : 1.0);
+            acc[DIAG_NEGATIVE] += (p < 0.0) ? 1.0 : 0.0;
+        }
+    }
+    __shared__ double red[DIAG_THREADS];
+    for (int k = 0; k < DIAG_COUNT; ++k) {
+        red[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int w = DIAG_THREADS / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                const double a = red[threadIdx.x], b = red[threadIdx.x + w];
+                const bool is_max = (k == DIAG_MAX_PHI || k == DIAG_MAX_PSI || k == DIAG_MAX_LAP);
+                red[threadIdx.x] = is_max ? fmax(a, b) : a + b;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partials[(long long)blockIdx.x * DIAG_COUNT + k] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void diag_final_kernel(const double* __restrict__ partials, int nparts,
+                                  double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= DIAG_COUNT) return;
+    const bool is_max = (k == DIAG_MAX_PHI || k == DIAG_MAX_PSI || k == DIAG_MAX_LAP);
+    double a = 0.0;
+    for (int b = 0; b < nparts; ++b) {
+        const double v = partials[(long long)b * DIAG_COUNT + k];
+        a = is_max ? fmax(a, v) : a + v;
+    }
+    out[k] = a;
+}
+
+template <typename T, int STAGE, int BY, bool COMP>
+hipError_t launch_one(const SolveDesc* descs, const Tile* tiles, int ntiles, long long kstep,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((stage_kernel<T, STAGE, BY, COMP>), dim3(ntiles), dim3(64 * BY), 0, s, descs,
+                       tiles, ntiles, kstep);
+    return hipGetLastError();
+}
+
+template <typename T, int BY, bool COMP>
+hipError_t launch_by_stage(int stage, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                           long long kstep, hipStream_t s) {
+    switch (stage) {
+        case 1: return launch_one<T, 1, BY, COMP>(descs, tiles, ntiles, kstep, s);
+        case 2: return launch_one<T, 2, BY, COMP>(descs, tiles, ntiles, kstep, s);
+        case 3: return launch_one<T, 3, BY, COMP>(descs, tiles, ntiles, kstep, s);
+        case 4: return launch_one<T, 4, BY, COMP>(descs, tiles, ntiles, kstep, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                 long long kstep, void* stream) {
+    if (ntiles <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (prec == PREC_F64) {
+        if (by == 8) e = launch_by_stage<double, 8, false>(stage, descs, tiles, ntiles, kstep, s);
+        else if (by == 16) e = launch_by_stage<double, 16, false>(stage, descs, tiles, ntiles, kstep, s);
+        else return (int)hipErrorInvalidValue;
+    } else {
+        if (by == 8) e = launch_by_stage<float, 8, true>(stage, descs, tiles, ntiles, kstep, s);
+        else if (by == 16) e = launch_by_stage<float, 16, true>(stage, descs, tiles, ntiles, kstep, s);
+        else return (int)hipErrorInvalidValue;
+    }
+    return (int)e;
+}
+
+int launch_tick(SolveDesc* descs, int count, long long k, void* stream) {
+    if (count <= 0) return 0;
+    hipLaunchKernelGGL(tick_kernel, dim3((count + 63) / 64), dim3(64), 0, (hipStream_t)stream, descs,
+                       count, k);
+    return (int)hipGetLastError();
+}
+
+int launch_set_target(SolveDesc* descs, int index, long long target, void* stream) {
+    hipLaunchKernelGGL(set_target_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, descs, index,
+                       target);
+    return (int)hipGetLastError();
+}
+
+int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream) {
+    hipLaunchKernelGGL(set_nstep_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, descs, index,
+                       nstep, target);
+    return (int)hipGetLastError();
+}
+
+static unsigned grid_for(long long total) {
+    long long blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,
+                  long long sz, void* hi, float* lo, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned g = grid_for((long long)nx * ny * nz);
+    const bool comp = prec == PREC_F32C;
+    if (src_dtype == 0) {
+        if (comp) hipLaunchKernelGGL((unpack_kernel<double, true>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, hi, lo);
+        else hipLaunchKernelGGL((unpack_kernel<double, false>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, hi, lo);
+    } else {
+        if (comp) hipLaunchKernelGGL((unpack_kernel<float, true>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, hi, lo);
+        else hipLaunchKernelGGL((unpack_kernel<float, false>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, hi, lo);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_pack(int prec, int dst_dtype, void* dst, int nx, int ny, int nz, long long sy,
+                long long sz, const void* hi, const float* lo, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned g = grid_for((long long)nx * ny * nz);
+    const bool comp = prec == PREC_F32C;
+    if (dst_dtype == 0) {
+        if (comp) hipLaunchKernelGGL((pack_kernel<double, true>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, hi, lo);
+        else hipLaunchKernelGGL((pack_kernel<double, false>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, hi, lo);
+    } else {
+        if (comp) hipLaunchKernelGGL((pack_kernel<float, true>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
+        else hipLaunchKernelGGL((pack_kernel<float, false>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
+    }
+    return (int)hipGetLastError();
+}
+
+int diag_partials_needed(int nx, int ny, int nz) {
+    const long long rows = (long long)ny * nz;
+    return (int)(rows < 4096 ? rows : 4096);
+}
+
+int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, double* partials,
+                       int nparts, double* out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == PREC_F32C)
+        hipLaunchKernelGGL((diag_kernel<true>), dim3(nparts), dim3(DIAG_THREADS), 0, s, desc, parity,
+                           c, partials);
+    else
+        hipLaunchKernelGGL((diag_kernel<false>), dim3(nparts), dim3(DIAG_THREADS), 0, s, desc, parity,
+                           c, partials);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, nparts, out);
+    return (int)hipGetLastError();
+}
+
+}  // namespace hb

@@ -1,0 +1,1102 @@
+// Host runtime of libhb: layout planning, device allocation, coefficient
+// tables, launch groups (one or many solves per stage launch), hipGraph step
+// replay, the autotuner and the C ABI declared in include/hb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.h"
+
+using namespace hb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(HB_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+    } while (0)
+
+#define HB_TRY(expr)                                  \
+    do {                                              \
+        int r_ = (expr);                              \
+        if (r_ != HB_OK) return r_;                   \
+    } while (0)
+
+int from_hip(int e, const char* what) {
+    if (e == 0) return HB_OK;
+    return fail(HB_E_HIP, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+// ---- layout ------------------------------------------------------------------
+
+struct Layout {
+    int nx, ny, nz;
+    size_t esz;             // bytes per element
+    long long sy, sz;       // row / plane pitch (elements)
+    long long origin_off;   // elements from field start to interior (0,0,0)
+    long long field_elems;  // elements per field (multiple of 256 bytes)
+    int nfields;            // 7 (FP64) or 9 (FP32c: + lo_phi, lo_psi)
+};
+
+Layout plan_layout(const hb_config& c) {
+    Layout L;
+    L.nx = c.n[0];
+    L.ny = c.n[1];
+    L.nz = c.n[2];
+    L.esz = c.precision == HB_F32C ? 4 : 8;
+    const long long line = 128 / (long long)L.esz;  // elements per 128-byte line
+    L.sy = round_up((long long)L.nx + 4, line);
+    L.sz = L.sy * ((long long)L.ny + 4);
+    L.origin_off = 2 * L.sz + 2 * L.sy + line;
+    const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
+                           L.nx + 2;
+    L.field_elems = round_up(last, 256 / (long long)L.esz);
+    L.nfields = c.precision == HB_F32C ? 9 : 7;
+    return L;
+}
+
+size_t field_bytes(const Layout& L) { return (size_t)L.field_elems * L.esz; }
+
+int validate(const hb_config* c) {
+    if (!c) return fail(HB_E_ARG, "config is NULL");
+    for (int d = 0; d < 3; ++d) {
+        if (c->n[d] < 1) return fail(HB_E_ARG, "n[%d] = %d must be >= 1", d, c->n[d]);
+        if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d]))
+            return fail(HB_E_ARG, "box axis %d must have hi > lo", d);
+    }
+    if ((long long)c->n[0] * c->n[1] * c->n[2] > (1LL << 40)) return fail(HB_E_ARG, "grid too large");
+    if (!std::isfinite(c->mu2) || !std::isfinite(c->lambda) || !std::isfinite(c->inv_L2) ||
+        !std::isfinite(c->t0))
+        return fail(HB_E_ARG, "coefficients must be finite");
+    if (!(c->dt > 0) || !std::isfinite(c->dt)) return fail(HB_E_ARG, "dt must be > 0");
+    if (c->inv_L2 < 0) return fail(HB_E_ARG, "inv_L2 must be >= 0");
+    if (c->precision != HB_F64 && c->precision != HB_F32C) return fail(HB_E_ARG, "bad precision");
+    if (!(c->flags & HB_ALLOW_UNSTABLE)) {
+        // RK4 is stable on the imaginary axis up to |z| = 2 sqrt(2); -Lap_h has
+        // spectral radius sum_d 16/(3 h_d^2) (symbol (1-cos)(7-cos)/3 <= 16/3)
+        double rho = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double h = (c->hi[d] - c->lo[d]) / c->n[d];
+            rho += 16.0 / (3.0 * h * h);
+        }
+        const double c0 = c->inv_L2 * std::exp(-2.0 * c->t0);
+        if (c->dt * std::sqrt(c0 * rho) > 2.0 * std::sqrt(2.0))
+            return fail(HB_E_CFL, "dt = %g exceeds the RK4 stability limit %g", c->dt,
+                        2.0 * std::sqrt(2.0) / std::sqrt(c0 * rho));
+    }
+    return HB_OK;
+}
+
+// ---- one solve -----------------------------------------------------------------
+
+struct Solve {
+    hb_config cfg{};
+    Layout L{};
+    char* mem = nullptr;          // all fields, one allocation
+    void* f[9] = {};              // origins: phi0, phi1, psi0, psi1, G1, G2, G3, lo_phi, lo_psi
+    double* ctab = nullptr;       // device c(t) table, 4 per step
+    long long ctab_steps = 0;
+    long long nstep = 0;          // host mirror of the device counter
+    long long target = 0;
+    bool has_initial = false;
+    double h[3]{};
+
+    ~Solve() {
+        if (mem) (void)hipFree(mem);
+        if (ctab) (void)hipFree(ctab);
+    }
+    int prec() const { return cfg.precision; }
+};
+
+size_t solve_footprint(const hb_config& c) {
+    const Layout L = plan_layout(c);
+    return field_bytes(L) * (size_t)L.nfields + 4096 * 4 * sizeof(double);
+}
+
+int solve_alloc(Solve& s, const hb_config& c, hipStream_t stream) {
+    s.cfg = c;
+    s.L = plan_layout(c);
+    for (int d = 0; d < 3; ++d) s.h[d] = (c.hi[d] - c.lo[d]) / c.n[d];
+    const size_t fb = field_bytes(s.L);
+    const size_t total = fb * (size_t)s.L.nfields;
+    hipError_t e = hipMalloc((void**)&s.mem, total);
+    if (e != hipSuccess) {
+        s.mem = nullptr;
+        (void)hipGetLastError();
+        return fail(HB_E_NOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+    }
+    // zero everything once: the halo stays zero for the life of the solve
+    HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
+    for (int k = 0; k < s.L.nfields; ++k) s.f[k] = s.mem + fb * k + (size_t)s.L.origin_off * s.L.esz;
+    return HB_OK;
+}
+
+// c(t) = inv_L2 exp(-2 t) at the stage times t_n, t_n + dt/2, t_n + dt/2,
+// t_n + dt with t_n = t0 + n dt (section 2.1 eq. (rhs) and the RK4 stages)
+void fill_ctab(const hb_config& c, long long n0, long long n1, std::vector<double>& out) {
+    out.resize((size_t)(n1 - n0) * 4);
+    for (long long n = n0; n < n1; ++n) {
+        const double t = c.t0 + (double)n * c.dt;
+        double* o = &out[(size_t)(n - n0) * 4];
+        o[0] = std::exp(-2.0 * t) * c.inv_L2;
+        o[1] = std::exp(-2.0 * (t + c.dt / 2.0)) * c.inv_L2;
+        o[2] = o[1];
+        o[3] = std::exp(-2.0 * (t + c.dt)) * c.inv_L2;
+    }
+}
+
+// make the device table cover steps [0, need); grows by doubling (synchronous)
+int ensure_ctab(Solve& s, long long need, hipStream_t stream, bool* reallocated) {
+    if (reallocated) *reallocated = false;
+    if (need <= s.ctab_steps) return HB_OK;
+    long long cap = std::max<long long>(4096, s.ctab_steps);
+    while (cap < need) cap *= 2;
+    std::vector<double> host;
+    fill_ctab(s.cfg, 0, cap, host);
+    double* nt = nullptr;
+    hipError_t e = hipMalloc((void**)&nt, host.size() * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HB_E_NOMEM, "coefficient table allocation failed");
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(nt, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (s.ctab) HIP_TRY(hipFree(s.ctab));
+    s.ctab = nt;
+    s.ctab_steps = cap;
+    if (reallocated) *reallocated = true;
+    return HB_OK;
+}
+
+SolveDesc make_desc(const Solve& s) {
+    SolveDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.y_phi[0] = s.f[0];
+    d.y_phi[1] = s.f[1];
+    d.y_psi[0] = s.f[2];
+    d.y_psi[1] = s.f[3];
+    d.g[0] = s.f[4];
+    d.g[1] = s.f[5];
+    d.g[2] = s.f[6];
+    d.lo_phi = (float*)s.f[7];
+    d.lo_psi = (float*)s.f[8];
+    d.ctab = s.ctab;
+    d.sy = s.L.sy;
+    d.sz = s.L.sz;
+    d.nx = s.L.nx;
+    d.ny = s.L.ny;
+    d.nz = s.L.nz;
+    d.prec = s.cfg.precision;
+    double sum = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double ih2 = 1.0 / (s.h[a] * s.h[a]);
+        sum += ih2;
+        d.w1[a] = 4.0 / 3.0 * ih2;
+        d.w2[a] = -1.0 / 12.0 * ih2;
+    }
+    d.w0 = -5.0 / 2.0 * sum;
+    d.mu2 = s.cfg.mu2;
+    d.lambda = s.cfg.lambda;
+    d.dt = s.cfg.dt;
+    d.hdt = s.cfg.dt / 2.0;
+    d.dt6 = s.cfg.dt / 6.0;
+    d.nstep = s.nstep;
+    d.target = s.target;
+    return d;
+}
+
+int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const void* psi, int mem,
+                 int dtype, hipStream_t stream) {
+    if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(HB_E_ARG, "bad dtype");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    const long long cnt = (long long)s.L.nx * s.L.ny * s.L.nz;
+    const size_t bytes = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
+    const void* src[2] = {phi, psi};
+    void* hi[2] = {s.f[slot_phi], s.f[slot_psi]};
+    float* lo[2] = {(float*)s.f[7], (float*)s.f[8]};
+    for (int k = 0; k < 2; ++k) {
+        const void* dsrc = src[k];
+        void* staged = nullptr;
+        if (src[k] && mem == HB_HOST) {
+            HIP_TRY(hipMalloc(&staged, bytes));
+            hipError_t e = hipMemcpyAsync(staged, src[k], bytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) {
+                (void)hipFree(staged);
+                return fail(HB_E_HIP, "H2D copy failed: %s", hipGetErrorString(e));
+            }
+            dsrc = staged;
+        }
+        int r = launch_unpack(s.prec(), dtype, dsrc, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, hi[k],
+                              lo[k], stream);
+        if (staged) {
+            // the host copy and the unpack must finish before the staging buffer goes
+            hipError_t e = hipStreamSynchronize(stream);
+            (void)hipFree(staged);
+            if (e != hipSuccess) return fail(HB_E_HIP, "sync failed: %s", hipGetErrorString(e));
+        }
+        HB_TRY(from_hip(r, "unpack"));
+    }
+    return HB_OK;
+}
+
+int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream_t stream) {
+    if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(HB_E_ARG, "bad dtype");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    const int par = (int)(s.nstep & 1);
+    const long long cnt = (long long)s.L.nx * s.L.ny * s.L.nz;
+    const size_t bytes = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
+    void* dst[2] = {phi, psi};
+    const void* hi[2] = {s.f[0 + par], s.f[2 + par]};
+    const float* lo[2] = {(const float*)s.f[7], (const float*)s.f[8]};
+    for (int k = 0; k < 2; ++k) {
+        if (!dst[k]) continue;
+        if (mem == HB_DEVICE) {
+            HB_TRY(from_hip(launch_pack(s.prec(), dtype, dst[k], s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz,
+                                        hi[k], lo[k], stream),
+                            "pack"));
+        } else {
+            void* staged = nullptr;
+            HIP_TRY(hipMalloc(&staged, bytes));
+            int r = launch_pack(s.prec(), dtype, staged, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, hi[k],
+                                lo[k], stream);
+            hipError_t e = r ? (hipError_t)r : hipMemcpyAsync(dst[k], staged, bytes,
+                                                              hipMemcpyDeviceToHost, stream);
+            hipError_t e2 = hipStreamSynchronize(stream);
+            (void)hipFree(staged);
+            if (e != hipSuccess) return fail(HB_E_HIP, "D2H failed: %s", hipGetErrorString(e));
+            if (e2 != hipSuccess) return fail(HB_E_HIP, "sync failed: %s", hipGetErrorString(e2));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    return HB_OK;
+}
+
+// ---- launch group: all solves of one precision, one launch per stage ---------
+
+constexpr int DEFAULT_BY = 8;
+
+int default_zc(const Layout& L, int by) {
+    // aim at >= ~2048 tiles for one solve, but keep the z-march long enough
+    // that its 4 warm-up planes stay a small overhead
+    const long long xy = (long long)((L.nx + TILE_X - 1) / TILE_X) * ((L.ny + by - 1) / by);
+    long long zc = L.nz;
+    while (zc > 32 && xy * ((L.nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+    return (int)std::max<long long>(1, zc);
+}
+
+struct Group {
+    int prec = HB_F64;
+    int by = DEFAULT_BY;
+    int zc = 0;  // 0 = default per solve
+    std::vector<Solve*> members;
+    SolveDesc* d_desc = nullptr;
+    int desc_cap = 0;
+    Tile* d_tiles = nullptr;
+    int tile_cap = 0;
+    int ntiles = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_k = 0;
+
+    ~Group() { release(); }
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        graph_k = 0;
+    }
+    void release() {
+        drop_graph();
+        if (d_desc) (void)hipFree(d_desc);
+        if (d_tiles) (void)hipFree(d_tiles);
+        d_desc = nullptr;
+        d_tiles = nullptr;
+        desc_cap = tile_cap = 0;
+    }
+};
+
+void make_tiles(const Solve& s, int solve_index, int by, int zc_req, std::vector<Tile>& out) {
+    const Layout& L = s.L;
+    const int zc = zc_req > 0 ? zc_req : default_zc(L, by);
+    // z-chunk major, then y, then x: consecutive tiles are spatial neighbours,
+    // and the XCD remap hands each XCD a contiguous run of them
+    for (int z0 = 0; z0 < L.nz; z0 += zc)
+        for (int y0 = 0; y0 < L.ny; y0 += by)
+            for (int x0 = 0; x0 < L.nx; x0 += TILE_X) {
+                Tile t;
+                std::memset(&t, 0, sizeof t);
+                t.solve = solve_index;
+                t.x0 = x0;
+                t.y0 = y0;
+                t.z0 = z0;
+                t.z1 = std::min(L.nz, z0 + zc);
+                out.push_back(t);
+            }
+}
+
+// (re)upload descriptors and the tile table; invalidates any captured graph
+int group_rebuild(Group& g, hipStream_t stream) {
+    g.drop_graph();
+    std::vector<SolveDesc> descs;
+    std::vector<Tile> tiles;
+    for (size_t i = 0; i < g.members.size(); ++i) {
+        descs.push_back(make_desc(*g.members[i]));
+        make_tiles(*g.members[i], (int)i, g.by, g.zc, tiles);
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    if ((int)descs.size() > g.desc_cap) {
+        if (g.d_desc) HIP_TRY(hipFree(g.d_desc));
+        g.d_desc = nullptr;
+        const int cap = std::max<int>(1, (int)descs.size());
+        if (hipMalloc((void**)&g.d_desc, cap * sizeof(SolveDesc)) != hipSuccess) {
+            (void)hipGetLastError();
+            g.desc_cap = 0;
+            return fail(HB_E_NOMEM, "descriptor allocation failed");
+        }
+        g.desc_cap = cap;
+    }
+    if ((int)tiles.size() > g.tile_cap) {
+        if (g.d_tiles) HIP_TRY(hipFree(g.d_tiles));
+        g.d_tiles = nullptr;
+        const int cap = std::max<int>(1, (int)tiles.size());
+        if (hipMalloc((void**)&g.d_tiles, cap * sizeof(Tile)) != hipSuccess) {
+            (void)hipGetLastError();
+            g.tile_cap = 0;
+            return fail(HB_E_NOMEM, "tile table allocation failed");
+        }
+        g.tile_cap = cap;
+    }
+    if (!descs.empty())
+        HIP_TRY(hipMemcpy(g.d_desc, descs.data(), descs.size() * sizeof(SolveDesc), hipMemcpyHostToDevice));
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpy(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    g.ntiles = (int)tiles.size();
+    return HB_OK;
+}
+
+int enqueue_steps(Group& g, long long k, hipStream_t stream) {
+    for (long long j = 0; j < k; ++j)
+        for (int st = 1; st <= 4; ++st)
+            HB_TRY(from_hip(launch_stage(g.prec, st, g.by, g.d_desc, g.d_tiles, g.ntiles, j, stream),
+                            "stage launch"));
+    return from_hip(launch_tick(g.d_desc, (int)g.members.size(), k, stream), "tick");
+}
+
+constexpr int GRAPH_STEPS = 16;
+
+int capture_graph(Group& g, hipStream_t stream) {
+    g.drop_graph();
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    int r = enqueue_steps(g, GRAPH_STEPS, stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (r != HB_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return fail(HB_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&g.gexec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(HB_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    g.graph = graph;
+    g.graph_k = GRAPH_STEPS;
+    return HB_OK;
+}
+
+// Advance every member of g by up to k steps; member targets must be set.
+int group_step(Group& g, long long k, bool use_graph, hipStream_t stream) {
+    if (g.members.empty() || k <= 0) return HB_OK;
+    long long done = 0;
+    if (use_graph && k >= GRAPH_STEPS) {
+        if (!g.gexec) HB_TRY(capture_graph(g, stream));
+        while (k - done >= GRAPH_STEPS) {
+            HIP_TRY(hipGraphLaunch(g.gexec, stream));
+            done += GRAPH_STEPS;
+        }
+    }
+    if (k > done) HB_TRY(enqueue_steps(g, k - done, stream));
+    for (Solve* s : g.members) s->nstep = std::min(s->nstep + k, s->target);
+    return HB_OK;
+}
+
+int group_step_timed(Group& g, long long k, hipStream_t stream, double* stage_ms) {
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+    double acc[4] = {0, 0, 0, 0};
+    int rc = HB_OK;
+    for (long long j = 0; j < k && rc == HB_OK; ++j) {
+        rc = from_hip(hipEventRecord(ev[0], stream), "event record");
+        for (int st = 1; st <= 4 && rc == HB_OK; ++st) {
+            rc = from_hip(launch_stage(g.prec, st, g.by, g.d_desc, g.d_tiles, g.ntiles, 0, stream),
+                          "stage launch");
+            if (rc == HB_OK) rc = from_hip(hipEventRecord(ev[st], stream), "event record");
+        }
+        if (rc == HB_OK) rc = from_hip(launch_tick(g.d_desc, (int)g.members.size(), 1, stream), "tick");
+        if (rc == HB_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = fail(HB_E_HIP, "event sync");
+        for (int st = 0; st < 4 && rc == HB_OK; ++st) {
+            float ms = 0;
+            rc = from_hip(hipEventElapsedTime(&ms, ev[st], ev[st + 1]), "event elapsed");
+            acc[st] += ms;
+        }
+        if (rc == HB_OK)
+            for (Solve* s : g.members) s->nstep = std::min(s->nstep + 1, s->target);
+    }
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    if (stage_ms)
+        for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i];
+    return rc;
+}
+
+int set_targets(Group& g, long long extra, hipStream_t stream, bool* tables_moved) {
+    // every member gets target = nstep + extra; tables must cover the target
+    bool moved = false;
+    for (size_t i = 0; i < g.members.size(); ++i) {
+        Solve* s = g.members[i];
+        s->target = s->nstep + extra;
+        bool re = false;
+        HB_TRY(ensure_ctab(*s, s->target, stream, &re));
+        moved = moved || re;
+    }
+    if (tables_moved) *tables_moved = moved;
+    return HB_OK;
+}
+
+}  // namespace
+
+// ---- C ABI: single solve -------------------------------------------------------
+
+struct hb_solver {
+    std::unique_ptr<Solve> s;
+    Group g;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool built = false;
+    double* d_partials = nullptr;
+    double* d_diag = nullptr;
+    int nparts = 0;
+    ~hb_solver() {
+        g.release();
+        if (d_partials) (void)hipFree(d_partials);
+        if (d_diag) (void)hipFree(d_diag);
+        s.reset();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+const char* hb_last_error(void) { return g_last_error.c_str(); }
+
+size_t hb_footprint(const hb_config* cfg) {
+    if (!cfg) return 0;
+    hb_config c = *cfg;
+    c.flags |= HB_ALLOW_UNSTABLE;
+    if (validate(&c) != HB_OK) return 0;
+    return solve_footprint(c);
+}
+
+int hb_create(const hb_config* cfg, hb_solver** out) {
+    g_last_error.clear();
+    if (!out) return fail(HB_E_ARG, "out is NULL");
+    *out = nullptr;
+    HB_TRY(validate(cfg));
+    auto h = std::make_unique<hb_solver>();
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    h->s = std::make_unique<Solve>();
+    HB_TRY(solve_alloc(*h->s, *cfg, h->stream));
+    HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
+    h->g.prec = cfg->precision;
+    h->g.members.push_back(h->s.get());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *out = h.release();
+    return HB_OK;
+}
+
+static int solver_rebuild(hb_solver* h) {
+    HB_TRY(group_rebuild(h->g, h->stream));
+    h->built = true;
+    return HB_OK;
+}
+
+int hb_set_state(hb_solver* h, const void* phi, const void* psi, int64_t n, int mem, int dtype) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (!phi) return fail(HB_E_ARG, "phi is NULL");
+    if (n < 0) return fail(HB_E_ARG, "step index must be >= 0");
+    Solve& s = *h->s;
+    const int par = (int)(n & 1);
+    HB_TRY(upload_state(s, 0 + par, 2 + par, phi, psi, mem, dtype, h->stream));
+    s.nstep = n;
+    s.target = n;
+    s.has_initial = true;
+    HB_TRY(ensure_ctab(s, n + 1, h->stream, nullptr));
+    HB_TRY(solver_rebuild(h));
+    return HB_OK;
+}
+
+int hb_set_initial(hb_solver* h, const void* phi0, const void* phi1, int mem, int dtype) {
+    return hb_set_state(h, phi0, phi1, 0, mem, dtype);
+}
+
+int hb_step(hb_solver* h, int64_t nsteps) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
+    if (nsteps == 0) return HB_OK;
+    bool moved = false;
+    HB_TRY(set_targets(h->g, nsteps, h->stream, &moved));
+    if (moved || !h->built) HB_TRY(solver_rebuild(h));
+    HB_TRY(from_hip(launch_set_target(h->g.d_desc, 0, h->s->target, h->stream), "set target"));
+    return group_step(h->g, nsteps, (h->s->cfg.flags & HB_USE_GRAPH) != 0, h->stream);
+}
+
+int hb_step_timed(hb_solver* h, int64_t nsteps, double* stage_ms) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
+    bool moved = false;
+    HB_TRY(set_targets(h->g, nsteps, h->stream, &moved));
+    if (moved || !h->built) HB_TRY(solver_rebuild(h));
+    HB_TRY(from_hip(launch_set_target(h->g.d_desc, 0, h->s->target, h->stream), "set target"));
+    return group_step_timed(h->g, nsteps, h->stream, stage_ms);
+}
+
+int hb_read(hb_solver* h, void* phi, void* phi_t, int mem, int dtype) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
+    return download_state(*h->s, phi, phi_t, mem, dtype, h->stream);
+}
+
+int hb_time(const hb_solver* h, double* t, int64_t* n) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    const Solve& s = *h->s;
+    if (t) *t = s.cfg.t0 + (double)s.nstep * s.cfg.dt;
+    if (n) *n = s.nstep;
+    return HB_OK;
+}
+
+int hb_sync(hb_solver* h) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return HB_OK;
+}
+
+int hb_diagnostics(hb_solver* h, hb_diag* out) {
+    if (!h || !out) return fail(HB_E_ARG, "NULL argument");
+    Solve& s = *h->s;
+    if (!s.has_initial) return fail(HB_E_STATE, "no initial data");
+    if (!h->built) HB_TRY(solver_rebuild(h));
+    if (!h->d_partials) {
+        h->nparts = diag_partials_needed(s.L.nx, s.L.ny, s.L.nz);
+        HIP_TRY(hipMalloc((void**)&h->d_partials, (size_t)h->nparts * DIAG_COUNT * sizeof(double)));
+        HIP_TRY(hipMalloc((void**)&h->d_diag, DIAG_COUNT * sizeof(double)));
+    }
+    const double t = s.cfg.t0 + (double)s.nstep * s.cfg.dt;
+    const double c = std::exp(-2.0 * t) * s.cfg.inv_L2;
+    HB_TRY(from_hip(launch_diagnostics(s.prec(), h->g.d_desc, (int)(s.nstep & 1), c, h->d_partials,
+                                       h->nparts, h->d_diag, h->stream),
+                    "diagnostics"));
+    double v[DIAG_COUNT];
+    HIP_TRY(hipMemcpyAsync(v, h->d_diag, sizeof v, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double vol = s.h[0] * s.h[1] * s.h[2];
+    out->t = t;
+    out->step = s.nstep;
+    out->integral = vol * v[DIAG_SUM_PHI];
+    out->l2_phi = std::sqrt(vol * v[DIAG_SUM_PHI2]);
+    out->l2_psi = std::sqrt(vol * v[DIAG_SUM_PSI2]);
+    out->linf_phi = v[DIAG_MAX_PHI];
+    out->linf_psi = v[DIAG_MAX_PSI];
+    out->lap_max = c * v[DIAG_MAX_LAP];
+    out->energy = vol * v[DIAG_ENERGY];
+    out->nonfinite = (int64_t)v[DIAG_NONFINITE];
+    out->negative = (int64_t)v[DIAG_NEGATIVE];
+    if (out->nonfinite > 0) return fail(HB_E_NONFINITE, "state holds %lld non-finite values",
+                                        (long long)out->nonfinite);
+    return HB_OK;
+}
+
+int hb_set_tiling(hb_solver* h, int by, int zc) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (by != 8 && by != 16) return fail(HB_E_ARG, "by must be 8 or 16");
+    if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
+    h->g.by = by;
+    h->g.zc = zc;
+    h->built = false;
+    return HB_OK;
+}
+
+int hb_destroy(hb_solver* h) {
+    if (!h) return HB_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return HB_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuner -------------------------------------------------------------------
+
+namespace {
+
+std::string tune_key(const Solve& s, int nmembers) {
+    hipDeviceProp_t p;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string name = "unknown";
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) name = p.gcnArchName;
+    std::ostringstream k;
+    k << name << "|prec" << s.cfg.precision << "|" << s.L.nx << "x" << s.L.ny << "x" << s.L.nz << "|m"
+      << nmembers;
+    return k.str();
+}
+
+// flat "key by zc" lines: simple, robust to partial writes
+bool cache_lookup(const std::string& key, int* by, int* zc) {
+    const char* path = std::getenv("HB_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    std::string k;
+    int b, z;
+    bool found = false;
+    while (f >> k >> b >> z)
+        if (k == key) {
+            *by = b;
+            *zc = z;
+            found = true;
+        }
+    return found;
+}
+
+void cache_store(const std::string& key, int by, int zc) {
+    const char* path = std::getenv("HB_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << by << " " << zc << "\n";
+}
+
+// Snapshot of the state fields of every member (current parity + low parts).
+struct Snapshot {
+    std::vector<void*> bufs;
+    ~Snapshot() {
+        for (void* b : bufs)
+            if (b) (void)hipFree(b);
+    }
+};
+
+int snapshot_take(Group& g, Snapshot& snap, hipStream_t stream) {
+    for (Solve* s : g.members) {
+        const size_t fb = field_bytes(s->L);
+        const int par = (int)(s->nstep & 1);
+        const int idx[4] = {0 + par, 2 + par, 7, 8};
+        const int nf = s->prec() == HB_F32C ? 4 : 2;
+        for (int k = 0; k < nf; ++k) {
+            void* b = nullptr;
+            HIP_TRY(hipMalloc(&b, fb));
+            snap.bufs.push_back(b);
+            char* base = (char*)s->f[idx[k]] - (size_t)s->L.origin_off * s->L.esz;
+            HIP_TRY(hipMemcpyAsync(b, base, fb, hipMemcpyDeviceToDevice, stream));
+        }
+    }
+    return HB_OK;
+}
+
+int snapshot_restore(Group& g, Snapshot& snap, const std::vector<long long>& nsteps, hipStream_t stream) {
+    size_t i = 0;
+    for (size_t m = 0; m < g.members.size(); ++m) {
+        Solve* s = g.members[m];
+        s->nstep = nsteps[m];
+        s->target = nsteps[m];
+        const size_t fb = field_bytes(s->L);
+        const int par = (int)(s->nstep & 1);
+        const int idx[4] = {0 + par, 2 + par, 7, 8};
+        const int nf = s->prec() == HB_F32C ? 4 : 2;
+        for (int k = 0; k < nf; ++k) {
+            char* base = (char*)s->f[idx[k]] - (size_t)s->L.origin_off * s->L.esz;
+            HIP_TRY(hipMemcpyAsync(base, snap.bufs[i++], fb, hipMemcpyDeviceToDevice, stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    return HB_OK;
+}
+
+int group_autotune(Group& g, int trial_steps, hipStream_t stream, int* best_by, int* best_zc) {
+    if (g.members.empty()) return fail(HB_E_STATE, "nothing to tune");
+    const Solve& s0 = *g.members[0];
+    const std::string key = tune_key(s0, (int)g.members.size());
+    int cb = 0, cz = 0;
+    if (cache_lookup(key, &cb, &cz)) {
+        g.by = cb;
+        g.zc = cz;
+        HB_TRY(group_rebuild(g, stream));
+        *best_by = cb;
+        *best_zc = cz;
+        return HB_OK;
+    }
+    std::vector<long long> saved;
+    for (Solve* s : g.members) saved.push_back(s->nstep);
+    Snapshot snap;
+    HB_TRY(snapshot_take(g, snap, stream));
+    std::vector<std::pair<int, int>> cand;
+    int maxz = 0;
+    for (Solve* s : g.members) maxz = std::max(maxz, s->L.nz);
+    for (int by : {8, 16})
+        for (int zc : {0, 16, 32, 64, 128})
+            if (zc <= maxz) cand.push_back({by, zc});
+    double best = 1e300;
+    int bb = DEFAULT_BY, bz = 0;
+    for (auto [by, zc] : cand) {
+        HB_TRY(snapshot_restore(g, snap, saved, stream));
+        g.by = by;
+        g.zc = zc;
+        bool moved;
+        HB_TRY(set_targets(g, trial_steps + 1, stream, &moved));
+        HB_TRY(group_rebuild(g, stream));
+        double ms[4];
+        HB_TRY(group_step_timed(g, 1, stream, ms));  // warm-up
+        HB_TRY(group_step_timed(g, trial_steps, stream, ms));
+        const double tot = ms[0] + ms[1] + ms[2] + ms[3];
+        if (tot < best) {
+            best = tot;
+            bb = by;
+            bz = zc;
+        }
+    }
+    HB_TRY(snapshot_restore(g, snap, saved, stream));
+    g.by = bb;
+    g.zc = bz;
+    HB_TRY(group_rebuild(g, stream));
+    cache_store(key, bb, bz);
+    *best_by = bb;
+    *best_zc = bz;
+    return HB_OK;
+}
+
+}  // namespace
+
+extern "C" int hb_autotune(hb_solver* h, int trial_steps, int* by, int* zc) {
+    if (!h) return fail(HB_E_ARG, "solver is NULL");
+    if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
+    if (trial_steps < 1) return fail(HB_E_ARG, "trial_steps must be >= 1");
+    int b = 0, z = 0;
+    HB_TRY(group_autotune(h->g, trial_steps, h->stream, &b, &z));
+    h->built = true;
+    if (by) *by = b;
+    if (zc) *zc = z;
+    return HB_OK;
+}
+
+// ---- C ABI: batched form ---------------------------------------------------------
+
+struct hb_batch {
+    std::vector<std::unique_ptr<Solve>> solves;
+    Group groups[2];  // by precision
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool built = false;
+    bool use_graph = false;
+    ~hb_batch() {
+        groups[0].release();
+        groups[1].release();
+        solves.clear();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** out) {
+    g_last_error.clear();
+    if (!out) return fail(HB_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !cfgs) return fail(HB_E_ARG, "need count >= 1 configs");
+    for (int i = 0; i < count; ++i) HB_TRY(validate(&cfgs[i]));
+    auto b = std::make_unique<hb_batch>();
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    b->groups[0].prec = HB_F64;
+    b->groups[1].prec = HB_F32C;
+    for (int i = 0; i < count; ++i) {
+        auto s = std::make_unique<Solve>();
+        HB_TRY(solve_alloc(*s, cfgs[i], b->stream));
+        HB_TRY(ensure_ctab(*s, 4096, b->stream, nullptr));
+        b->groups[cfgs[i].precision].members.push_back(s.get());
+        b->use_graph = b->use_graph || (cfgs[i].flags & HB_USE_GRAPH);
+        b->solves.push_back(std::move(s));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    *out = b.release();
+    return HB_OK;
+}
+
+int hb_batch_set_initial(hb_batch* b, int i, const void* phi0, const void* phi1, int mem, int dtype) {
+    if (!b || i < 0 || i >= (int)b->solves.size()) return fail(HB_E_ARG, "bad batch index");
+    if (!phi0) return fail(HB_E_ARG, "phi0 is NULL");
+    Solve& s = *b->solves[i];
+    HB_TRY(upload_state(s, 0, 2, phi0, phi1, mem, dtype, b->stream));
+    s.nstep = 0;
+    s.target = 0;
+    s.has_initial = true;
+    b->built = false;
+    return HB_OK;
+}
+
+int hb_batch_step(hb_batch* b, int64_t nsteps) {
+    if (!b) return fail(HB_E_ARG, "batch is NULL");
+    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    for (auto& s : b->solves)
+        if (!s->has_initial) return fail(HB_E_STATE, "a solve has no initial data");
+    if (nsteps == 0) return HB_OK;
+    for (Group& g : b->groups) {
+        if (g.members.empty()) continue;
+        bool moved = false;
+        HB_TRY(set_targets(g, nsteps, b->stream, &moved));
+        if (moved || !b->built) HB_TRY(group_rebuild(g, b->stream));
+        for (size_t i = 0; i < g.members.size(); ++i)
+            HB_TRY(from_hip(launch_set_target(g.d_desc, (int)i, g.members[i]->target, b->stream),
+                            "set target"));
+    }
+    b->built = true;
+    for (Group& g : b->groups) HB_TRY(group_step(g, nsteps, b->use_graph, b->stream));
+    return HB_OK;
+}
+
+int hb_batch_read(hb_batch* b, int i, void* phi, void* phi_t, int mem, int dtype) {
+    if (!b || i < 0 || i >= (int)b->solves.size()) return fail(HB_E_ARG, "bad batch index");
+    if (!b->solves[i]->has_initial) return fail(HB_E_STATE, "no initial data");
+    return download_state(*b->solves[i], phi, phi_t, mem, dtype, b->stream);
+}
+
+int hb_batch_sync(hb_batch* b) {
+    if (!b) return fail(HB_E_ARG, "batch is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return HB_OK;
+}
+
+int hb_batch_set_tiling(hb_batch* b, int by, int zc) {
+    if (!b) return fail(HB_E_ARG, "batch is NULL");
+    if (by != 8 && by != 16) return fail(HB_E_ARG, "by must be 8 or 16");
+    if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
+    for (Group& g : b->groups) {
+        g.by = by;
+        g.zc = zc;
+    }
+    b->built = false;
+    return HB_OK;
+}
+
+int hb_batch_destroy(hb_batch* b) {
+    if (!b) return HB_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+    return HB_OK;
+}
+
+}  // extern "C"
+
+// ---- C ABI: served form (continuous batching) -------------------------------------
+
+struct hb_pool {
+    struct Slot {
+        std::unique_ptr<Solve> s;
+        size_t bytes = 0;
+        bool busy = false;
+        bool done = false;
+        bool reported = false;
+    };
+    std::vector<Slot> slots;
+    size_t budget = 0, in_use = 0;
+    Group groups[2];
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool dirty = true;
+    ~hb_pool() {
+        groups[0].release();
+        groups[1].release();
+        slots.clear();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out) {
+    g_last_error.clear();
+    if (!out) return fail(HB_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || hbm_budget == 0) return fail(HB_E_ARG, "need max_slots >= 1 and a budget");
+    auto p = std::make_unique<hb_pool>();
+    p->slots.resize(max_slots);
+    p->budget = hbm_budget;
+    if (stream) {
+        p->stream = (hipStream_t)stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+        p->own_stream = true;
+    }
+    p->groups[0].prec = HB_F64;
+    p->groups[1].prec = HB_F32C;
+    *out = p.release();
+    return HB_OK;
+}
+
+int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void* phi1, int mem,
+                  int dtype, int64_t steps, int* slot) {
+    if (!p || !slot) return fail(HB_E_ARG, "NULL argument");
+    *slot = -1;
+    HB_TRY(validate(cfg));
+    if (!phi0) return fail(HB_E_ARG, "phi0 is NULL");
+    if (steps < 0) return fail(HB_E_ARG, "steps must be >= 0");
+    const size_t need = solve_footprint(*cfg) + (size_t)std::max<long long>(steps, 4096) * 32;
+    int free_slot = -1;
+    for (size_t i = 0; i < p->slots.size(); ++i)
+        if (!p->slots[i].busy) {
+            free_slot = (int)i;
+            break;
+        }
+    if (free_slot < 0) return fail(HB_E_BUSY, "no free slot");
+    if (need > p->budget - p->in_use) return fail(HB_E_BUSY, "HBM budget exhausted");
+    auto s = std::make_unique<Solve>();
+    HB_TRY(solve_alloc(*s, *cfg, p->stream));
+    HB_TRY(ensure_ctab(*s, steps + 1, p->stream, nullptr));
+    HB_TRY(upload_state(*s, 0, 2, phi0, phi1, mem, dtype, p->stream));
+    s->nstep = 0;
+    s->target = steps;
+    s->has_initial = true;
+    hb_pool::Slot& sl = p->slots[free_slot];
+    sl.s = std::move(s);
+    sl.bytes = need;
+    sl.busy = true;
+    sl.done = (steps == 0);
+    sl.reported = false;
+    p->in_use += need;
+    p->dirty = true;
+    *slot = free_slot;
+    return HB_OK;
+}
+
+static int pool_rebuild(hb_pool* p) {
+    for (Group& g : p->groups) g.members.clear();
+    for (auto& sl : p->slots)
+        if (sl.busy && !sl.done) p->groups[sl.s->prec()].members.push_back(sl.s.get());
+    for (Group& g : p->groups) {
+        if (g.members.empty()) {
+            g.drop_graph();
+            g.ntiles = 0;
+            continue;
+        }
+        HB_TRY(group_rebuild(g, p->stream));
+    }
+    p->dirty = false;
+    return HB_OK;
+}
+
+int hb_pool_advance(hb_pool* p, int k) {
+    if (!p) return fail(HB_E_ARG, "pool is NULL");
+    if (k < 0) return fail(HB_E_ARG, "k must be >= 0");
+    if (p->dirty) HB_TRY(pool_rebuild(p));
+    for (Group& g : p->groups) HB_TRY(group_step(g, k, false, p->stream));
+    bool finished = false;
+    for (auto& sl : p->slots)
+        if (sl.busy && !sl.done && sl.s->nstep >= sl.s->target) {
+            sl.done = true;
+            finished = true;
+        }
+    if (finished) p->dirty = true;
+    return HB_OK;
+}
+
+int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone) {
+    if (!p || !ndone) return fail(HB_E_ARG, "NULL argument");
+    int n = 0;
+    for (size_t i = 0; i < p->slots.size(); ++i) {
+        auto& sl = p->slots[i];
+        if (sl.busy && sl.done && !sl.reported && n < cap) {
+            if (done) done[n] = (int)i;
+            sl.reported = true;
+            ++n;
+        }
+    }
+    *ndone = n;
+    return HB_OK;
+}
+
+int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use) {
+    if (!p) return fail(HB_E_ARG, "pool is NULL");
+    int a = 0;
+    for (auto& sl : p->slots)
+        if (sl.busy && !sl.done) ++a;
+    if (active) *active = a;
+    if (in_use) *in_use = p->in_use;
+    return HB_OK;
+}
+
+int hb_pool_read(hb_pool* p, int slot, void* phi, void* phi_t, int mem, int dtype) {
+    if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot].busy)
+        return fail(HB_E_ARG, "bad slot");
+    return download_state(*p->slots[slot].s, phi, phi_t, mem, dtype, p->stream);
+}
+
+int hb_pool_release(hb_pool* p, int slot) {
+    if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot].busy)
+        return fail(HB_E_ARG, "bad slot");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    auto& sl = p->slots[slot];
+    const bool active = !sl.done;
+    p->in_use -= sl.bytes;
+    sl.s.reset();
+    sl.busy = false;
+    sl.done = false;
+    sl.reported = false;
+    sl.bytes = 0;
+    if (active) p->dirty = true;
+    return HB_OK;
+}
+
+int hb_pool_destroy(hb_pool* p) {
+    if (!p) return HB_OK;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    delete p;
+    return HB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,367 @@
+"""ctypes binding of libhb (include/hb.h): same names, argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of libhb.so; this module only
+converts Python/NumPy/torch arguments into the C ABI's plain pointers and
+raises ``HBError`` on a negative status.  Arrays are C-ordered [nz][ny][nx]:
+NumPy arrays are passed as host memory, CUDA/HIP torch tensors as device
+memory.  There is no CPU fallback: ``load()`` fails when the library is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhb.so")
+
+HB_OK = 0
+HB_E_ARG, HB_E_CFL, HB_E_NOMEM, HB_E_HIP, HB_E_STATE, HB_E_BUSY, HB_E_NONFINITE = range(-1, -8, -1)
+HB_F64, HB_F32C = 0, 1
+HB_HOST, HB_DEVICE = 0, 1
+HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
+HB_ALLOW_UNSTABLE, HB_USE_GRAPH = 1, 2
+
+_NAMES = {HB_E_ARG: "HB_E_ARG", HB_E_CFL: "HB_E_CFL", HB_E_NOMEM: "HB_E_NOMEM",
+          HB_E_HIP: "HB_E_HIP", HB_E_STATE: "HB_E_STATE", HB_E_BUSY: "HB_E_BUSY",
+          HB_E_NONFINITE: "HB_E_NONFINITE"}
+
+
+class HBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class hb_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("mu2", ctypes.c_double), ("lambda_", ctypes.c_double), ("inv_L2", ctypes.c_double),
+                ("t0", ctypes.c_double), ("dt", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("stream", ctypes.c_void_p)]
+
+
+class hb_diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("step", ctypes.c_int64), ("integral", ctypes.c_double),
+                ("l2_phi", ctypes.c_double), ("l2_psi", ctypes.c_double),
+                ("linf_phi", ctypes.c_double), ("linf_psi", ctypes.c_double),
+                ("lap_max", ctypes.c_double), ("energy", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64), ("negative", ctypes.c_int64)]
+
+    def asdict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_SIGS = {
+    "hb_create": [ctypes.POINTER(hb_config), ctypes.POINTER(_P)],
+    "hb_set_initial": [_P, _P, _P, _I, _I],
+    "hb_set_state": [_P, _P, _P, _I64, _I, _I],
+    "hb_step": [_P, _I64],
+    "hb_step_timed": [_P, _I64, ctypes.POINTER(ctypes.c_double)],
+    "hb_read": [_P, _P, _P, _I, _I],
+    "hb_time": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)],
+    "hb_sync": [_P],
+    "hb_diagnostics": [_P, ctypes.POINTER(hb_diag)],
+    "hb_set_tiling": [_P, _I, _I],
+    "hb_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "hb_destroy": [_P],
+    "hb_footprint": [ctypes.POINTER(hb_config)],
+    "hb_last_error": [],
+    "hb_batch_create": [_I, ctypes.POINTER(hb_config), _P, ctypes.POINTER(_P)],
+    "hb_batch_set_initial": [_P, _I, _P, _P, _I, _I],
+    "hb_batch_step": [_P, _I64],
+    "hb_batch_read": [_P, _I, _P, _P, _I, _I],
+    "hb_batch_sync": [_P],
+    "hb_batch_set_tiling": [_P, _I, _I],
+    "hb_batch_destroy": [_P],
+    "hb_pool_create": [ctypes.c_size_t, _I, _P, ctypes.POINTER(_P)],
+    "hb_pool_admit": [_P, ctypes.POINTER(hb_config), _P, _P, _I, _I, _I64, ctypes.POINTER(_I)],
+    "hb_pool_advance": [_P, _I],
+    "hb_pool_poll": [_P, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)],
+    "hb_pool_stats": [_P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_size_t)],
+    "hb_pool_read": [_P, _I, _P, _P, _I, _I],
+    "hb_pool_release": [_P, _I],
+    "hb_pool_destroy": [_P],
+}
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhb.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhb.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_size_t if name == "hb_footprint" else (
+            ctypes.c_char_p if name == "hb_last_error" else ctypes.c_int)
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise HBError(rc, load().hb_last_error().decode())
+    return rc
+
+
+def _arr(a):
+    """(pointer, mem, dtype, keepalive) of a NumPy array or a torch tensor."""
+    if a is None:
+        return None, HB_HOST, HB_DTYPE_F64, None
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("arrays must be C-contiguous")
+        if a.dtype == np.float64:
+            dt = HB_DTYPE_F64
+        elif a.dtype == np.float32:
+            dt = HB_DTYPE_F32
+        else:
+            raise TypeError(f"unsupported dtype {a.dtype}")
+        return a.ctypes.data, HB_HOST, dt, a
+    import torch
+    if isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        if a.dtype == torch.float64:
+            dt = HB_DTYPE_F64
+        elif a.dtype == torch.float32:
+            dt = HB_DTYPE_F32
+        else:
+            raise TypeError(f"unsupported dtype {a.dtype}")
+        return a.data_ptr(), (HB_DEVICE if a.is_cuda else HB_HOST), dt, a
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def make_config(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], mu2: float,
+                lam: float, dt: float, t0: float = 0.0, inv_L2: float = 1.0,
+                precision: int = HB_F64, flags: int = 0, stream: Optional[int] = None) -> hb_config:
+    c = hb_config()
+    c.n[:] = [int(v) for v in n]
+    c.lo[:] = [float(v) for v in lo]
+    c.hi[:] = [float(v) for v in hi]
+    c.mu2, c.lambda_, c.inv_L2, c.t0, c.dt = float(mu2), float(lam), float(inv_L2), float(t0), float(dt)
+    c.precision, c.flags, c.stream = int(precision), int(flags), stream
+    return c
+
+
+def config_from_workload(w, precision: int = HB_F64, flags: int = 0, stream=None) -> hb_config:
+    return make_config(w.n, w.lo, w.hi, w.mu2, w.lam, w.dt, w.t0, w.inv_L2, precision, flags, stream)
+
+
+# ---- single solve ---------------------------------------------------------------
+
+def hb_create(cfg: hb_config) -> int:
+    h = _P()
+    _check(load().hb_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def hb_set_initial(h: int, phi0, phi1=None) -> None:
+    p0, m0, d0, _k0 = _arr(phi0)
+    p1, m1, d1, _k1 = _arr(phi1)
+    if phi1 is not None and (m0, d0) != (m1, d1):
+        raise ValueError("phi0 and phi1 must share memory kind and dtype")
+    _check(load().hb_set_initial(h, p0, p1, m0, d0))
+
+
+def hb_set_state(h: int, phi, psi, n: int) -> None:
+    p0, m0, d0, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(psi)
+    if psi is not None and (m0, d0) != (m1, d1):
+        raise ValueError("phi and psi must share memory kind and dtype")
+    _check(load().hb_set_state(h, p0, p1, int(n), m0, d0))
+
+
+def hb_step(h: int, nsteps: int) -> None:
+    _check(load().hb_step(h, int(nsteps)))
+
+
+def hb_step_timed(h: int, nsteps: int):
+    ms = (ctypes.c_double * 4)()
+    _check(load().hb_step_timed(h, int(nsteps), ms))
+    return list(ms)
+
+
+def hb_read(h: int, phi=None, phi_t=None) -> None:
+    """Fill the given output arrays (NumPy host or torch device)."""
+    ref = phi if phi is not None else phi_t
+    if ref is None:
+        return
+    p0, m, d, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(phi_t)
+    if phi is None:
+        m, d = m1, d1
+    _check(load().hb_read(h, p0, p1, m, d))
+
+
+def hb_time(h: int):
+    t = ctypes.c_double()
+    n = _I64()
+    _check(load().hb_time(h, ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
+
+
+def hb_sync(h: int) -> None:
+    _check(load().hb_sync(h))
+
+
+def hb_diagnostics(h: int, allow_nonfinite: bool = False) -> dict:
+    d = hb_diag()
+    rc = load().hb_diagnostics(h, ctypes.byref(d))
+    if rc == HB_E_NONFINITE and allow_nonfinite:
+        return d.asdict()
+    _check(rc)
+    return d.asdict()
+
+
+def hb_set_tiling(h: int, by: int, zc: int) -> None:
+    _check(load().hb_set_tiling(h, int(by), int(zc)))
+
+
+def hb_autotune(h: int, trial_steps: int = 5):
+    by, zc = _I(), _I()
+    _check(load().hb_autotune(h, int(trial_steps), ctypes.byref(by), ctypes.byref(zc)))
+    return by.value, zc.value
+
+
+def hb_destroy(h: int) -> None:
+    if h:
+        _check(load().hb_destroy(h))
+
+
+def hb_footprint(cfg: hb_config) -> int:
+    return int(load().hb_footprint(ctypes.byref(cfg)))
+
+
+def hb_last_error() -> str:
+    return load().hb_last_error().decode()
+
+
+# ---- batched form -----------------------------------------------------------------
+
+def hb_batch_create(cfgs: Sequence[hb_config], stream=None) -> int:
+    arr = (hb_config * len(cfgs))(*cfgs)
+    b = _P()
+    _check(load().hb_batch_create(len(cfgs), arr, stream, ctypes.byref(b)))
+    return b.value
+
+
+def hb_batch_set_initial(b: int, i: int, phi0, phi1=None) -> None:
+    p0, m0, d0, _k0 = _arr(phi0)
+    p1, _m1, _d1, _k1 = _arr(phi1)
+    _check(load().hb_batch_set_initial(b, int(i), p0, p1, m0, d0))
+
+
+def hb_batch_step(b: int, nsteps: int) -> None:
+    _check(load().hb_batch_step(b, int(nsteps)))
+
+
+def hb_batch_read(b: int, i: int, phi=None, phi_t=None) -> None:
+    p0, m, d, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(phi_t)
+    if phi is None:
+        m, d = m1, d1
+    _check(load().hb_batch_read(b, int(i), p0, p1, m, d))
+
+
+def hb_batch_sync(b: int) -> None:
+    _check(load().hb_batch_sync(b))
+
+
+def hb_batch_set_tiling(b: int, by: int, zc: int) -> None:
+    _check(load().hb_batch_set_tiling(b, int(by), int(zc)))
+
+
+def hb_batch_destroy(b: int) -> None:
+    if b:
+        _check(load().hb_batch_destroy(b))
+
+
+# ---- served form ----------------------------------------------------------------------
+
+def hb_pool_create(hbm_budget: int, max_slots: int, stream=None) -> int:
+    p = _P()
+    _check(load().hb_pool_create(int(hbm_budget), int(max_slots), stream, ctypes.byref(p)))
+    return p.value
+
+
+def hb_pool_admit(p: int, cfg: hb_config, phi0, phi1, steps: int) -> Optional[int]:
+    """Returns the slot, or None when the pool is busy (HB_E_BUSY)."""
+    p0, m0, d0, _k0 = _arr(phi0)
+    p1, _m1, _d1, _k1 = _arr(phi1)
+    slot = _I()
+    rc = load().hb_pool_admit(p, ctypes.byref(cfg), p0, p1, m0, d0, int(steps), ctypes.byref(slot))
+    if rc == HB_E_BUSY:
+        return None
+    _check(rc)
+    return slot.value
+
+
+def hb_pool_advance(p: int, k: int) -> None:
+    _check(load().hb_pool_advance(p, int(k)))
+
+
+def hb_pool_poll(p: int, cap: int = 1024):
+    buf = (_I * cap)()
+    n = _I()
+    _check(load().hb_pool_poll(p, buf, cap, ctypes.byref(n)))
+    return list(buf[: n.value])
+
+
+def hb_pool_stats(p: int):
+    a = _I()
+    u = ctypes.c_size_t()
+    _check(load().hb_pool_stats(p, ctypes.byref(a), ctypes.byref(u)))
+    return a.value, u.value
+
+
+def hb_pool_read(p: int, slot: int, phi=None, phi_t=None) -> None:
+    p0, m, d, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(phi_t)
+    if phi is None:
+        m, d = m1, d1
+    _check(load().hb_pool_read(p, int(slot), p0, p1, m, d))
+
+
+def hb_pool_release(p: int, slot: int) -> None:
+    _check(load().hb_pool_release(p, int(slot)))
+
+
+def hb_pool_destroy(p: int) -> None:
+    if p:
+        _check(load().hb_pool_destroy(p))
+
+
+# ---- convenience (marshalling only) -------------------------------------------------
+
+def solve_host(w, nsteps: Optional[int] = None, precision: int = HB_F64, flags: int = 0,
+               tiling=None):
+    """Run a synth_inputs.Workload through the GPU path with host arrays in and out."""
+    p0, p1 = w.initial()
+    h = hb_create(config_from_workload(w, precision, flags))
+    try:
+        if tiling is not None:
+            hb_set_tiling(h, *tiling)
+        hb_set_initial(h, p0, p1)
+        hb_step(h, w.steps if nsteps is None else nsteps)
+        phi = np.empty_like(p0)
+        psi = np.empty_like(p0)
+        hb_read(h, phi, psi)
+    finally:
+        hb_destroy(h)
+    return phi, psi

@@ -1,0 +1,225 @@
+"""GPU path (libhb through its C ABI) against the FP64 CPU oracle.
+
+Bar: FP64 state-vector relative max norm <= 1e-12 (elementwise comparison);
+FP32c (FP32 storage/stencil, compensated state) <= 1e-5 against the FP64
+oracle.  Sizes span several 64 x BY tiles, ragged x/y/z tails and z-chunks.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32C = 1e-5
+
+
+def run_gpu(hb, w, nsteps=None, precision=0, flags=0, tiling=None):
+    return hb.solve_host(w, nsteps, precision=precision, flags=flags, tiling=tiling)
+
+
+def test_config1_full(hb, oracle_mod):
+    w = si.config1()
+    g = run_gpu(hb, w)
+    r = oracle.solve_workload(w)
+    err = oracle.rel_maxnorm(*g, *r)
+    print(f"cube32 100 steps: rel err {err:.3e}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("shape,tiling", [
+    ((70, 21, 13), None),          # 2 x-tiles (64 + 6), ragged y, default z
+    ((130, 17, 40), (8, 7)),       # 3 x-tiles, ragged z-chunks of 7
+    ((64, 32, 24), (16, 5)),       # exact x tile, BY = 16
+    ((200, 9, 11), (16, 0)),       # BY larger than a ragged y tail
+    ((5, 3, 30), (8, 4)),          # narrower than one tile
+])
+def test_ragged_shapes(hb, oracle_mod, shape, tiling):
+    w = si.small_case(*shape, seed=sum(shape), steps=12)
+    g = run_gpu(hb, w, tiling=tiling)
+    r = oracle.solve_workload(w)
+    err = oracle.rel_maxnorm(*g, *r)
+    print(f"{shape} tiling {tiling}: rel err {err:.3e}")
+    assert err <= TOL64
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 3), (1, 40, 1), (3, 3, 70)])
+def test_degenerate_shapes(hb, oracle_mod, shape):
+    w = si.small_case(*shape, seed=3, steps=6)
+    g = run_gpu(hb, w)
+    r = oracle.solve_workload(w)
+    assert oracle.rel_maxnorm(*g, *r) <= TOL64
+
+
+def test_zero_data_stays_zero(hb):
+    w = si.small_case(40, 10, 10, steps=5)
+    w.phi0 = w.phi1 = None
+    phi, psi = run_gpu(hb, w)
+    assert not np.any(phi) and not np.any(psi)
+
+
+@pytest.mark.parametrize("mu2,lam,t0,inv_L2", [(9.0, 2.0, 0.0, 1 / 25), (1.0, -1.0, 0.3, 1.0),
+                                               (0.1, 0.1, -0.2, 0.5), (-1.0, 0.0, 1.0, 2.0)])
+def test_coefficients(hb, oracle_mod, mu2, lam, t0, inv_L2):
+    w = si.small_case(66, 12, 10, seed=11, steps=10, mu2=mu2, lam=lam, t0=t0, inv_L2=inv_L2)
+    g = run_gpu(hb, w)
+    r = oracle.solve_workload(w)
+    assert oracle.rel_maxnorm(*g, *r) <= TOL64
+
+
+def test_anisotropic_spacing(hb, oracle_mod):
+    w = si.small_case(40, 20, 12, seed=2, steps=8)
+    w.hi = (w.hi[0], w.hi[1] * 1.7, w.hi[2] * 0.6)
+    g = run_gpu(hb, w)
+    r = oracle.solve_workload(w)
+    assert oracle.rel_maxnorm(*g, *r) <= TOL64
+
+
+def test_fp32c_against_fp64_oracle(hb, oracle_mod):
+    w = si.small_case(96, 40, 24, seed=5, steps=40)
+    g = run_gpu(hb, w, precision=hb.HB_F32C)
+    r = oracle.solve_workload(w)
+    err = oracle.rel_maxnorm(*g, *r)
+    print(f"fp32c rel err {err:.3e}")
+    assert err <= TOL32C
+
+
+def test_graph_replay_bitwise(hb):
+    w = si.small_case(70, 20, 18, seed=8, steps=37)
+    a = run_gpu(hb, w)
+    b = run_gpu(hb, w, flags=hb.HB_USE_GRAPH)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_tiling_does_not_change_results(hb):
+    w = si.small_case(90, 30, 33, seed=9, steps=6)
+    ref = run_gpu(hb, w, tiling=(8, 0))
+    for t in [(16, 0), (8, 5), (16, 11), (8, 1)]:
+        got = run_gpu(hb, w, tiling=t)
+        np.testing.assert_array_equal(ref[0], got[0])
+        np.testing.assert_array_equal(ref[1], got[1])
+
+
+def test_repeatable_bitwise(hb):
+    w = si.small_case(80, 24, 20, seed=10, steps=9)
+    a = run_gpu(hb, w)
+    b = run_gpu(hb, w)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_bitwise(hb, precision):
+    w = si.small_case(70, 16, 12, seed=12, steps=10)
+    p0, p1 = w.initial()
+    cfg = hb.config_from_workload(w, precision)
+    h = hb.hb_create(cfg)
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, 10)
+        full_phi, full_psi = np.empty_like(p0), np.empty_like(p0)
+        hb.hb_read(h, full_phi, full_psi)
+    finally:
+        hb.hb_destroy(h)
+    h = hb.hb_create(cfg)
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, 4)
+        if precision == 0:
+            a, b = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_read(h, a, b)
+            hb.hb_destroy(h)
+            h = hb.hb_create(cfg)
+            hb.hb_set_state(h, a, b, 4)
+        hb.hb_step(h, 3)
+        hb.hb_step(h, 3)
+        assert hb.hb_time(h)[1] == 10
+        phi, psi = np.empty_like(p0), np.empty_like(p0)
+        hb.hb_read(h, phi, psi)
+    finally:
+        hb.hb_destroy(h)
+    np.testing.assert_array_equal(phi, full_phi)
+    np.testing.assert_array_equal(psi, full_psi)
+
+
+def test_device_pointers_torch(hb, oracle_mod):
+    import torch
+    w = si.small_case(68, 10, 9, seed=13, steps=7)
+    p0, p1 = w.initial()
+    dev = torch.device("cuda:0")
+    t0 = torch.from_numpy(p0).to(dev)
+    t1 = torch.from_numpy(p1).to(dev)
+    s = torch.cuda.current_stream()
+    h = hb.hb_create(hb.config_from_workload(w, stream=s.cuda_stream or None))
+    try:
+        hb.hb_set_initial(h, t0, t1)
+        hb.hb_step(h, w.steps)
+        o0 = torch.empty_like(t0)
+        o1 = torch.empty(t0.shape, dtype=torch.float32, device=dev)
+        hb.hb_read(h, o0, None)
+        hb.hb_read(h, None, o1)
+        torch.cuda.synchronize()
+    finally:
+        hb.hb_destroy(h)
+    r = oracle.solve_workload(w)
+    assert np.max(np.abs(o0.cpu().numpy() - r[0])) <= TOL64 * np.max(np.abs(r[0]))
+    np.testing.assert_allclose(o1.cpu().numpy(), r[1].astype(np.float32), rtol=1e-6, atol=1e-7)
+
+
+def test_diagnostics_match_oracle(hb, oracle_mod):
+    from oracle.diagnostics import diagnostics
+    w = si.small_case(50, 30, 20, seed=14, steps=5, inv_L2=0.7, t0=0.1)
+    p0, p1 = w.initial()
+    h = hb.hb_create(hb.config_from_workload(w))
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, w.steps)
+        d = hb.hb_diagnostics(h)
+        phi, psi = np.empty_like(p0), np.empty_like(p0)
+        hb.hb_read(h, phi, psi)
+    finally:
+        hb.hb_destroy(h)
+    ref = diagnostics(phi, psi, w.h, w.mu2, w.lam, w.t0 + w.steps * w.dt, w.inv_L2)
+    for k in ("integral", "linf_phi", "linf_psi", "l2_phi", "l2_psi", "lap_max", "energy"):
+        assert d[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-14), k
+    assert d["nonfinite"] == 0 and d["negative"] == ref["negative"]
+
+
+def test_errors(hb):
+    w = si.small_case(16, 16, 16, steps=1)
+    h = hb.hb_create(hb.config_from_workload(w))
+    try:
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_step(h, 1)
+        assert e.value.code == hb.HB_E_STATE
+    finally:
+        hb.hb_destroy(h)
+    bad = hb.config_from_workload(w)
+    bad.dt = 10.0
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_create(bad)
+    assert e.value.code == hb.HB_E_CFL
+    bad = hb.config_from_workload(w)
+    bad.n[1] = 0
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_create(bad)
+    assert e.value.code == hb.HB_E_ARG
+
+
+def test_nonfinite_detected(hb):
+    w = si.small_case(20, 20, 20, steps=2)
+    p0, p1 = w.initial()
+    p0[3, 4, 5] = np.nan
+    h = hb.hb_create(hb.config_from_workload(w))
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, 1)
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_diagnostics(h)
+        assert e.value.code == hb.HB_E_NONFINITE
+        assert hb.hb_diagnostics(h, allow_nonfinite=True)["nonfinite"] > 1
+    finally:
+        hb.hb_destroy(h)
