@@ -2,18 +2,20 @@
 
 Workload: 256^3 interior points on [-16,16]^3 (h = 0.125), mu^2 = 2,
 lambda = 1, phi0 = 8 seeded Gaussians (seed 0), phi1 = 0, dt = 0.005 (the
-2000-step single-solve configuration).  A "step" is one full RK4 step (4 fused
-stage kernels + the step-counter tick) over the whole grid; inputs are
+2000-step single-solve configuration).  A "step" is one full RK4 step (2 fused
+stage-pair kernels + the step-counter tick) over the whole grid; inputs are
 resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      -- dominant kernel (stage 4: 7 field passes = 56 B/point FP64)
-                   algorithmic bytes / its average duration, from HIP events
-                   on the solver's stream, against 8 TB/s;
+  roofline      -- dominant kernel (stage pair 3+4: 6 field passes = 48 B/point
+                   FP64) algorithmic bytes / its average duration, from HIP
+                   events on the solver's stream, against 8 TB/s;
   cpu_baseline  -- the FP64 CPU oracle on a bounded number of steps of the
                    same grid, on this host's cores;
   forms         -- the same step rate for the FP32c form (same grid) when
-                   --forms is given.
+                   --forms is given;
+  hbm_probe     -- with --probe, the streamed-bandwidth ceiling measured by
+                   the library's copy and 5-read/2-write probe kernels.
 """
 import argparse
 import json
@@ -25,14 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per point per stage (field passes x element size)
-PASSES = {1: 3, 2: 4, 3: 5, 4: 7}
-
-
-def stage_bytes(stage, precision):
-    if precision == 0:
-        return PASSES[stage] * 8
-    return PASSES[stage] * 4 + (16 if stage == 4 else 0)
+# Algorithmic bytes per interior point for each kernel of one RK4 step
+# (field passes x element size).  Stage-pair scheme: kernel A (stages 1+2)
+# reads Y_phi, Y_psi and writes G1, G2 (4 passes); kernel B (stages 3+4)
+# reads Y_phi, Y_psi, G1, G2 and writes Y'_phi, Y'_psi (6 passes); FP32c adds
+# the read and write of the two FP32 low parts in kernel B (16 B).
+KERNEL_BYTES = {0: [32, 48], 1: [16, 40]}
+# the per-stage (19-pass) scheme: 3, 4, 5, 7 passes; FP32c + 16 B in stage 4
+STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 
 
 def run_gpu(w, precision, steps, warmup, timed_stage_steps):
@@ -81,6 +83,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="also measure the streamed-HBM ceiling (copy and 5-read/2-write probes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no "
@@ -91,11 +95,12 @@ def main():
     w = si.config2(n=args.n)
     N = w.points
     elapsed, stage_ms, diag = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps)
+    stage_ms = stage_ms[:2]
     rate = N * args.steps / elapsed
-    dom = max(range(4), key=lambda s: stage_ms[s])
-    dom_bytes = stage_bytes(dom + 1, 0) * N
+    dom = max(range(2), key=lambda s: stage_ms[s])
+    dom_bytes = KERNEL_BYTES[0][dom] * N
     achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    step_alg = sum(stage_bytes(s, 0) for s in range(1, 5)) * N
+    step_alg = sum(KERNEL_BYTES[0]) * N
     out = {
         "metric": "RK4 grid-point updates/s (FP64, fused 13-point stencil stages)",
         "value": rate,
@@ -114,8 +119,9 @@ def main():
                    "grid": [args.n] * 3, "dt": w.dt, "precision": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"stage {dom + 1}",
-                     "stage_ms": stage_ms,
+                     "kernel": ["pair_kernel stages 1+2", "pair_kernel stages 3+4"][dom],
+                     "kernel_ms": stage_ms,
+                     "bytes_per_point": KERNEL_BYTES[0],
                      "step_alg_GBps": step_alg / (elapsed / args.steps) / 1e9,
                      "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
@@ -123,7 +129,14 @@ def main():
     if args.forms:
         e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
-                                 "stage_ms": ms32}}
+                                 "kernel_ms": ms32[:2],
+                                 "step_alg_GBps": sum(KERNEL_BYTES[1]) * N / (e32 / args.steps) / 1e9}}
+    if args.probe:
+        from paper_1803_01291_amd import hb
+        gib = 1 << 30
+        out["hbm_probe"] = {"copy_GBps": hb.hb_probe_bandwidth(0, gib, 20),
+                            "read5_write2_GBps": hb.hb_probe_bandwidth(2, gib // 2, 20),
+                            "bytes_per_array": [gib, gib // 2]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -64,6 +64,9 @@ extern "C" {
 /* hb_config.flags */
 #define HB_ALLOW_UNSTABLE 1u /* skip the dt stability check                    */
 #define HB_USE_GRAPH 2u      /* replay captured hipGraphs of several steps     */
+#define HB_STAGEWISE 4u      /* one launch per RK4 stage (19 field passes per  */
+                             /* step) instead of the default stage-pair       */
+                             /* launches (10 passes); bitwise-equal results   */
 
 typedef struct hb_config {
     int32_t n[3];        /* interior points along x, y, z (each >= 1)              */
@@ -117,13 +120,16 @@ int hb_set_initial(hb_solver* s, const void* phi0, const void* phi1, int mem, in
 /* Restore a checkpoint: state (phi, psi) at step n (t = t0 + n dt). */
 int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int mem, int dtype);
 
-/* Enqueue nsteps RK4 steps (4 fused stage kernels each) on the solver's stream
- * and return without waiting.  HB_E_STATE before initial data. */
+/* Enqueue nsteps RK4 steps on the solver's stream and return without waiting.
+ * Each step is 2 fused stage-pair kernels (stages 1+2, then 3+4), or 4
+ * per-stage kernels with HB_STAGEWISE, plus a tiny step-counter kernel.
+ * HB_E_STATE before initial data. */
 int hb_step(hb_solver* s, int64_t nsteps);
 
 /* Like hb_step, but waits after every step and returns the summed device time
- * of each of the 4 stage kernels in stage_ms[0..3] (HIP events on the
- * solver's stream around each launch).  For measurement. */
+ * of each kernel of the step in stage_ms[0..3] (HIP events on the solver's
+ * stream around each launch): the 2 stage-pair kernels in [0..1] (with [2..3]
+ * zero), or the 4 per-stage kernels with HB_STAGEWISE.  For measurement. */
 int hb_step_timed(hb_solver* s, int64_t nsteps, double* stage_ms);
 
 /* Wait for the solver's stream, then copy the interior state out.  Either
@@ -146,8 +152,8 @@ int hb_set_tiling(hb_solver* s, int by, int zc);
 
 /* Time every candidate tile shape for `trial_steps` steps on the current
  * state, keep the fastest, and restore the state (bitwise).  The choice is
- * cached per (device, precision, grid) in the JSON file named by the
- * HB_TUNE_CACHE environment variable, if set. */
+ * cached per (device, precision, grid) in the text file named by the
+ * HB_TUNE_CACHE environment variable, if set (one "key by zc" line each). */
 int hb_autotune(hb_solver* s, int trial_steps, int* by, int* zc);
 
 /* Free everything (NULL-safe). */
@@ -198,6 +204,16 @@ int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use);
 int hb_pool_read(hb_pool* p, int slot, void* phi, void* phi_t, int mem, int dtype);
 int hb_pool_release(hb_pool* p, int slot);
 int hb_pool_destroy(hb_pool* p);
+
+/* ---- measurement ----------------------------------------------------------- */
+
+/* Streamed-bandwidth probe on the current device (the achievable HBM ceiling
+ * for kernels shaped like the stage kernels).  kind 0: copy (1 read + 1 write
+ * array), 1: add (2 reads + 1 write), 2: 5 reads + 2 writes (the FP64 stage-4
+ * mix).  Each array holds bytes_per_array bytes (library-allocated, freed
+ * before return).  *gbps = bytes moved / time of `iters` launches after one
+ * warm-up launch.  Waits; uses the NULL stream. */
+int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, double* gbps);
 
 #ifdef __cplusplus
 }

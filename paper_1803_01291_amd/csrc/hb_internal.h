@@ -47,6 +47,10 @@ constexpr int TILE_X = 64;
 // Launchers (implemented in hb_kernels.hip).  All are asynchronous on `stream`.
 int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile* tiles,
                  int ntiles, long long kstep, void* stream);
+// Stage-pair kernels: pair 0 = stages 1+2 (writes G1, G2), pair 1 = stages 3+4
+// (writes the next state).  Bitwise equal to the four per-stage launches.
+int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                long long kstep, void* stream);
 int launch_tick(SolveDesc* descs, int count, long long k, void* stream);
 int launch_set_target(SolveDesc* descs, int index, long long target, void* stream);
 int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream);
@@ -66,5 +70,10 @@ enum { DIAG_SUM_PHI = 0, DIAG_SUM_PHI2, DIAG_SUM_PSI2, DIAG_MAX_PHI, DIAG_MAX_PS
 int diag_partials_needed(int nx, int ny, int nz);
 int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, double* partials,
                        int nparts, double* out, void* stream);
+
+// Bandwidth probe: kind 0 = copy (1 read, 1 write), 1 = add (2 reads, 1 write),
+// 2 = 5 reads + 2 writes (the FP64 stage-4 stream mix).  n16 elements of 16 B.
+int launch_probe(int kind, void* const* in, void* const* out, long long n16, int blocks,
+                 void* stream);
 
 }  // namespace hb

@@ -232,6 +232,202 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
     }
 }
 
+// Stage-pair kernels.  Because phi_t = psi, the stencil input of stage s is
+// built from G_{s-2} at most (S_phi,2 from Y only, S_phi,4 from Y and G2), so
+// stages 1+2 and stages 3+4 can each be evaluated in one pass over the grid:
+//   PAIR 0: reads Y_phi, Y_psi (both stenciled)          -> writes G1, G2
+//   PAIR 1: reads Y_phi, Y_psi, G1, G2 (all stenciled)   -> writes Y'_phi, Y'_psi
+//           (G3 lives only in registers)
+// 10 field passes per step instead of 19.  The per-point arithmetic and its
+// order are those of the per-stage kernels above, so results are bitwise equal.
+// Two stencil inputs per pass: two LDS planes and two register z-queues.
+template <typename T, int PAIR, int BY, bool COMP>
+__global__ void __launch_bounds__(64 * BY)
+pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
+            long long kstep) {
+    constexpr int LX = TILE_X + 4;
+    constexpr int LY = BY + 4;
+    constexpr int NHALO = 4 * TILE_X + 4 * BY;
+    static_assert(NHALO <= 64 * BY, "one halo column per thread at most");
+    __shared__ T sa[2][LY][LX];
+    __shared__ T sb[2][LY][LX];
+
+    const Tile tl = tiles[xcd_remap(blockIdx.x, ntiles)];
+    const SolveDesc* __restrict__ d = descs + tl.solve;
+    const long long n = d->nstep + kstep;
+    if (n >= d->target) return;  // uniform over the block
+    const int par = (int)(n & 1);
+
+    const T* __restrict__ Yp = (const T*)d->y_phi[par];
+    const T* __restrict__ Ys = (const T*)d->y_psi[par];
+    const T* __restrict__ G1 = (const T*)d->g[0];
+    const T* __restrict__ G2 = (const T*)d->g[1];
+    const long long sy = d->sy, sz = d->sz;
+    const int nx = d->nx, ny = d->ny;
+
+    const T ca = (T)d->ctab[4 * n + 2 * PAIR];
+    const T cb = (T)d->ctab[4 * n + 2 * PAIR + 1];
+    const T w0 = (T)d->w0;
+    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
+    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
+    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
+    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x = tl.x0 + tx, y = tl.y0 + ty;
+    const bool own_ld = (x < nx + 2) && (y < ny + 2);
+    const bool own_st = (x < nx) && (y < ny);
+    const long long own_off = (long long)y * sy + x;
+
+    bool has_halo = false, halo_ld = false;
+    int hlx = 0, hly = 0;
+    long long halo_off = 0;
+    if (tid < NHALO) {
+        int hx, hy;
+        if (tid < 4 * TILE_X) {
+            const int r = tid >> 6;
+            hy = (r < 2) ? tl.y0 - 2 + r : tl.y0 + BY + (r - 2);
+            hx = tl.x0 + (tid & 63);
+        } else {
+            const int h = tid - 4 * TILE_X;
+            const int k = h & 3;
+            hy = tl.y0 + (h >> 2);
+            hx = (k < 2) ? tl.x0 - 2 + k : tl.x0 + TILE_X + (k - 2);
+        }
+        has_halo = true;
+        halo_ld = (hx >= -2) && (hx < nx + 2) && (hy >= -2) && (hy < ny + 2);
+        hlx = hx - tl.x0 + 2;
+        hly = hy - tl.y0 + 2;
+        halo_off = (long long)hy * sy + hx;
+    }
+
+    // raw fields of one point: PAIR 0 needs Y_phi, Y_psi; PAIR 1 also G1, G2
+    struct Rec {
+        T p, s, g1, g2;
+    };
+    auto load_at = [&](long long o, bool ok) {
+        Rec r;
+        r.p = ldg(Yp, o, ok);
+        r.s = ldg(Ys, o, ok);
+        r.g1 = (PAIR == 1) ? ldg(G1, o, ok) : T(0);
+        r.g2 = (PAIR == 1) ? ldg(G2, o, ok) : T(0);
+        return r;
+    };
+    auto load_own = [&](int z) { return load_at((long long)z * sz + own_off, own_ld); };
+    auto load_halo = [&](int z) { return load_at((long long)z * sz + halo_off, has_halo && halo_ld); };
+    // the two stencil inputs: PAIR 0: S_phi,1 and S_phi,2; PAIR 1: S_phi,3 and S_phi,4
+    auto formA = [&](const Rec& r) -> T {
+        if constexpr (PAIR == 0) return r.p;
+        return r.p + hdt * (r.s + hdt * r.g1);
+    };
+    auto formB = [&](const Rec& r) -> T {
+        if constexpr (PAIR == 0) return r.p + hdt * r.s;
+        return r.p + dtT * (r.s + hdt * r.g2);
+    };
+
+    const int z0 = tl.z0, z1 = tl.z1;
+    Rec rm2 = load_own(z0 - 2), rm1 = load_own(z0 - 1);
+    Rec r0 = load_own(z0), r1 = load_own(z0 + 1), r2 = load_own(z0 + 2);
+    Rec h0 = load_halo(z0);
+    T a0 = formA(rm2), a1 = formA(rm1), a2 = formA(r0), a3 = formA(r1);
+    T b0 = formB(rm2), b1 = formB(rm1), b2 = formB(r0), b3 = formB(r1);
+    float lp = 0.f, ls = 0.f, lpn = 0.f, lsn = 0.f;
+    if constexpr (COMP && PAIR == 1) {
+        lp = ldg(d->lo_phi, (long long)z0 * sz + own_off, own_ld);
+        ls = ldg(d->lo_psi, (long long)z0 * sz + own_off, own_ld);
+    }
+    int buf = 0;
+
+    for (int z = z0; z < z1; ++z) {
+        Rec rn{}, hn{};
+        if (z + 3 <= z1 + 1) rn = load_own(z + 3);
+        if (z + 1 < z1) hn = load_halo(z + 1);
+        if constexpr (COMP && PAIR == 1) {
+            if (z + 1 < z1) {
+                lpn = ldg(d->lo_phi, (long long)(z + 1) * sz + own_off, own_ld);
+                lsn = ldg(d->lo_psi, (long long)(z + 1) * sz + own_off, own_ld);
+            }
+        }
+
+        const T a4 = formA(r2), b4 = formB(r2);
+        sa[buf][ty + 2][tx + 2] = a2;
+        sb[buf][ty + 2][tx + 2] = b2;
+        if (has_halo) {
+            sa[buf][hly][hlx] = formA(h0);
+            sb[buf][hly][hlx] = formB(h0);
+        }
+        __syncthreads();
+
+        const int lx = tx + 2, ly = ty + 2;
+        const T(*PA)[LX] = sa[buf];
+        const T(*PB)[LX] = sb[buf];
+        T lapA = w0 * a2;
+        lapA += w1x * (PA[ly][lx - 1] + PA[ly][lx + 1]);
+        lapA += w2x * (PA[ly][lx - 2] + PA[ly][lx + 2]);
+        lapA += w1y * (PA[ly - 1][lx] + PA[ly + 1][lx]);
+        lapA += w2y * (PA[ly - 2][lx] + PA[ly + 2][lx]);
+        lapA += w1z * (a1 + a3);
+        lapA += w2z * (a0 + a4);
+        T lapB = w0 * b2;
+        lapB += w1x * (PB[ly][lx - 1] + PB[ly][lx + 1]);
+        lapB += w2x * (PB[ly][lx - 2] + PB[ly][lx + 2]);
+        lapB += w1y * (PB[ly - 1][lx] + PB[ly + 1][lx]);
+        lapB += w2y * (PB[ly - 2][lx] + PB[ly + 2][lx]);
+        lapB += w1z * (b1 + b3);
+        lapB += w2z * (b0 + b4);
+
+        const long long o = (long long)z * sz + own_off;
+        if constexpr (PAIR == 0) {
+            // stage 1: S_psi,1 = Y_psi;  stage 2: S_psi,2 = Y_psi + dt/2 G1
+            const T SA = a2, SB = b2;
+            const T g1 = -T(3) * r0.s + ca * lapA + mu2 * SA - lam * SA * SA * SA;
+            const T spsi2 = r0.s + hdt * g1;
+            const T g2 = -T(3) * spsi2 + cb * lapB + mu2 * SB - lam * SB * SB * SB;
+            if (own_st) {
+                ((T*)d->g[0])[o] = g1;
+                ((T*)d->g[1])[o] = g2;
+            }
+        } else {
+            // stage 3: S_psi,3 = Y_psi + dt/2 G2;  stage 4: S_psi,4 = Y_psi + dt G3
+            const T SA = a2, SB = b2;
+            const T spsi3 = r0.s + hdt * r0.g2;
+            const T g3 = -T(3) * spsi3 + ca * lapA + mu2 * SA - lam * SA * SA * SA;
+            const T spsi4 = r0.s + dtT * g3;
+            const T g4 = -T(3) * spsi4 + cb * lapB + mu2 * SB - lam * SB * SB * SB;
+            if (own_st) {
+                if constexpr (!COMP) {
+                    const double dt6 = d->dt6;
+                    const T k2 = r0.s + hdt * r0.g1;
+                    const T k3 = r0.s + hdt * r0.g2;
+                    ((T*)d->y_phi[par ^ 1])[o] = r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi4);
+                    ((T*)d->y_psi[par ^ 1])[o] =
+                        r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * g3 + g4);
+                } else {
+                    const double hd = d->hdt, dd = d->dt, dt6 = d->dt6;
+                    const double p = (double)r0.p + (double)lp;
+                    const double s = (double)r0.s + (double)ls;
+                    const double e1 = r0.g1, e2 = r0.g2, e3 = g3, e4 = g4;
+                    const double k2 = s + hd * e1, k3 = s + hd * e2, k4 = s + dd * e3;
+                    const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
+                    const double ns_ = s + dt6 * (e1 + 2.0 * e2 + 2.0 * e3 + e4);
+                    const float hp = (float)np_, hs = (float)ns_;
+                    ((float*)d->y_phi[par ^ 1])[o] = hp;
+                    ((float*)d->y_psi[par ^ 1])[o] = hs;
+                    d->lo_phi[o] = (float)(np_ - (double)hp);
+                    d->lo_psi[o] = (float)(ns_ - (double)hs);
+                }
+            }
+        }
+        a0 = a1; a1 = a2; a2 = a3; a3 = a4;
+        b0 = b1; b1 = b2; b2 = b3; b3 = b4;
+        r0 = r1; r1 = r2; r2 = rn;
+        h0 = hn;
+        lp = lpn; ls = lsn;
+        buf ^= 1;
+    }
+}
+
 __global__ void tick_kernel(SolveDesc* descs, int count, long long k) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
@@ -368,6 +564,27 @@ __global__ void diag_final_kernel(const double* __restrict__ partials, int npart
     out[k] = a;
 }
 
+// ---- bandwidth probe: R streamed reads and W streamed writes of 16-byte
+// elements, grid-stride, no reuse (the measured HBM ceiling for kernels shaped
+// like the stage kernels; also the plain copy used to calibrate byte counters)
+template <int R, int W>
+__global__ void __launch_bounds__(256)
+probe_kernel(const double2* __restrict__ a0, const double2* __restrict__ a1,
+             const double2* __restrict__ a2, const double2* __restrict__ a3,
+             const double2* __restrict__ a4, double2* __restrict__ o0, double2* __restrict__ o1,
+             long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double2 v = a0[i];
+        if constexpr (R > 1) { const double2 t = a1[i]; v.x += t.x; v.y += t.y; }
+        if constexpr (R > 2) { const double2 t = a2[i]; v.x += t.x; v.y += t.y; }
+        if constexpr (R > 3) { const double2 t = a3[i]; v.x += t.x; v.y += t.y; }
+        if constexpr (R > 4) { const double2 t = a4[i]; v.x += t.x; v.y += t.y; }
+        o0[i] = v;
+        if constexpr (W > 1) o1[i] = make_double2(v.y, v.x);
+    }
+}
+
 template <typename T, int STAGE, int BY, bool COMP>
 hipError_t launch_one(const SolveDesc* descs, const Tile* tiles, int ntiles, long long kstep,
                       hipStream_t s) {
@@ -388,6 +605,18 @@ hipError_t launch_by_stage(int stage, const SolveDesc* descs, const Tile* tiles,
     }
 }
 
+template <typename T, int BY, bool COMP>
+hipError_t launch_pair_t(int pair, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                         long long kstep, hipStream_t s) {
+    if (pair == 0)
+        hipLaunchKernelGGL((pair_kernel<T, 0, BY, COMP>), dim3(ntiles), dim3(64 * BY), 0, s, descs,
+                           tiles, ntiles, kstep);
+    else
+        hipLaunchKernelGGL((pair_kernel<T, 1, BY, COMP>), dim3(ntiles), dim3(64 * BY), 0, s, descs,
+                           tiles, ntiles, kstep);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
@@ -402,6 +631,24 @@ int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile
     } else {
         if (by == 8) e = launch_by_stage<float, 8, true>(stage, descs, tiles, ntiles, kstep, s);
         else if (by == 16) e = launch_by_stage<float, 16, true>(stage, descs, tiles, ntiles, kstep, s);
+        else return (int)hipErrorInvalidValue;
+    }
+    return (int)e;
+}
+
+int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                long long kstep, void* stream) {
+    if (ntiles <= 0) return 0;
+    if (pair != 0 && pair != 1) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (prec == PREC_F64) {
+        if (by == 8) e = launch_pair_t<double, 8, false>(pair, descs, tiles, ntiles, kstep, s);
+        else if (by == 16) e = launch_pair_t<double, 16, false>(pair, descs, tiles, ntiles, kstep, s);
+        else return (int)hipErrorInvalidValue;
+    } else {
+        if (by == 8) e = launch_pair_t<float, 8, true>(pair, descs, tiles, ntiles, kstep, s);
+        else if (by == 16) e = launch_pair_t<float, 16, true>(pair, descs, tiles, ntiles, kstep, s);
         else return (int)hipErrorInvalidValue;
     }
     return (int)e;
@@ -458,6 +705,22 @@ int launch_pack(int prec, int dst_dtype, void* dst, int nx, int ny, int nz, long
     } else {
         if (comp) hipLaunchKernelGGL((pack_kernel<float, true>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
         else hipLaunchKernelGGL((pack_kernel<float, false>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_probe(int kind, void* const* in, void* const* out, long long n16, int blocks,
+                 void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const double2* a[5];
+    for (int k = 0; k < 5; ++k) a[k] = (const double2*)in[k];
+    double2* o0 = (double2*)out[0];
+    double2* o1 = (double2*)out[1];
+    switch (kind) {
+        case 0: hipLaunchKernelGGL((probe_kernel<1, 1>), dim3(blocks), dim3(256), 0, s, a[0], a[1], a[2], a[3], a[4], o0, o1, n16); break;
+        case 1: hipLaunchKernelGGL((probe_kernel<2, 1>), dim3(blocks), dim3(256), 0, s, a[0], a[1], a[2], a[3], a[4], o0, o1, n16); break;
+        case 2: hipLaunchKernelGGL((probe_kernel<5, 2>), dim3(blocks), dim3(256), 0, s, a[0], a[1], a[2], a[3], a[4], o0, o1, n16); break;
+        default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }

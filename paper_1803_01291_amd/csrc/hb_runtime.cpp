@@ -301,19 +301,21 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
 
 // ---- launch group: all solves of one precision, one launch per stage ---------
 
-constexpr int DEFAULT_BY = 8;
+constexpr int DEFAULT_BY = 16;
 
 int default_zc(const Layout& L, int by) {
-    // aim at >= ~2048 tiles for one solve, but keep the z-march long enough
-    // that its 4 warm-up planes stay a small overhead
+    // z-marches of 64 planes (4 warm-up planes = 6% extra stencil reads), cut
+    // shorter only while one solve would give fewer than 256 tiles (one
+    // 16-wave block per CU); measured best on 256^3 and 512^3 grids
     const long long xy = (long long)((L.nx + TILE_X - 1) / TILE_X) * ((L.ny + by - 1) / by);
-    long long zc = L.nz;
-    while (zc > 32 && xy * ((L.nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+    long long zc = std::min<long long>(L.nz, 64);
+    while (zc > 8 && xy * ((L.nz + zc - 1) / zc) < 256) zc = (zc + 1) / 2;
     return (int)std::max<long long>(1, zc);
 }
 
 struct Group {
     int prec = HB_F64;
+    bool stagewise = false;  // 4 per-stage launches instead of 2 stage-pair launches
     int by = DEFAULT_BY;
     int zc = 0;  // 0 = default per solve
     std::vector<Solve*> members;
@@ -403,11 +405,20 @@ int group_rebuild(Group& g, hipStream_t stream) {
     return HB_OK;
 }
 
+int kernels_per_step(const Group& g) { return g.stagewise ? 4 : 2; }
+
+// kernel i of one step (stage i+1, or stage pair i)
+int launch_step_kernel(const Group& g, int i, long long kstep, hipStream_t stream) {
+    if (g.stagewise)
+        return from_hip(launch_stage(g.prec, i + 1, g.by, g.d_desc, g.d_tiles, g.ntiles, kstep, stream),
+                        "stage launch");
+    return from_hip(launch_pair(g.prec, i, g.by, g.d_desc, g.d_tiles, g.ntiles, kstep, stream),
+                    "stage-pair launch");
+}
+
 int enqueue_steps(Group& g, long long k, hipStream_t stream) {
     for (long long j = 0; j < k; ++j)
-        for (int st = 1; st <= 4; ++st)
-            HB_TRY(from_hip(launch_stage(g.prec, st, g.by, g.d_desc, g.d_tiles, g.ntiles, j, stream),
-                            "stage launch"));
+        for (int i = 0; i < kernels_per_step(g); ++i) HB_TRY(launch_step_kernel(g, i, j, stream));
     return from_hip(launch_tick(g.d_desc, (int)g.members.size(), k, stream), "tick");
 }
 
@@ -455,16 +466,16 @@ int group_step_timed(Group& g, long long k, hipStream_t stream, double* stage_ms
     for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ev[i]));
     double acc[4] = {0, 0, 0, 0};
     int rc = HB_OK;
+    const int nk = kernels_per_step(g);
     for (long long j = 0; j < k && rc == HB_OK; ++j) {
         rc = from_hip(hipEventRecord(ev[0], stream), "event record");
-        for (int st = 1; st <= 4 && rc == HB_OK; ++st) {
-            rc = from_hip(launch_stage(g.prec, st, g.by, g.d_desc, g.d_tiles, g.ntiles, 0, stream),
-                          "stage launch");
-            if (rc == HB_OK) rc = from_hip(hipEventRecord(ev[st], stream), "event record");
+        for (int i = 0; i < nk && rc == HB_OK; ++i) {
+            rc = launch_step_kernel(g, i, 0, stream);
+            if (rc == HB_OK) rc = from_hip(hipEventRecord(ev[i + 1], stream), "event record");
         }
         if (rc == HB_OK) rc = from_hip(launch_tick(g.d_desc, (int)g.members.size(), 1, stream), "tick");
-        if (rc == HB_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = fail(HB_E_HIP, "event sync");
-        for (int st = 0; st < 4 && rc == HB_OK; ++st) {
+        if (rc == HB_OK && hipEventSynchronize(ev[nk]) != hipSuccess) rc = fail(HB_E_HIP, "event sync");
+        for (int st = 0; st < nk && rc == HB_OK; ++st) {
             float ms = 0;
             rc = from_hip(hipEventElapsedTime(&ms, ev[st], ev[st + 1]), "event elapsed");
             acc[st] += ms;
@@ -542,6 +553,7 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
     HB_TRY(solve_alloc(*h->s, *cfg, h->stream));
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
+    h->g.stagewise = (cfg->flags & HB_STAGEWISE) != 0;
     h->g.members.push_back(h->s.get());
     HIP_TRY(hipStreamSynchronize(h->stream));
     *out = h.release();
@@ -860,6 +872,7 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
         HB_TRY(solve_alloc(*s, cfgs[i], b->stream));
         HB_TRY(ensure_ctab(*s, 4096, b->stream, nullptr));
         b->groups[cfgs[i].precision].members.push_back(s.get());
+        if (cfgs[i].flags & HB_STAGEWISE) b->groups[cfgs[i].precision].stagewise = true;
         b->use_graph = b->use_graph || (cfgs[i].flags & HB_USE_GRAPH);
         b->solves.push_back(std::move(s));
     }
@@ -1100,3 +1113,47 @@ int hb_pool_destroy(hb_pool* p) {
 }
 
 }  // extern "C"
+
+// ---- measurement: streamed-bandwidth probe -----------------------------------------
+
+extern "C" int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, double* gbps) {
+    if (kind < 0 || kind > 2 || iters < 1 || bytes_per_array < 4096 || !gbps)
+        return fail(HB_E_ARG, "bad probe arguments");
+    const int nin = kind == 0 ? 1 : kind == 1 ? 2 : 5;
+    const int nout = kind == 2 ? 2 : 1;
+    const long long n16 = (long long)(bytes_per_array / 16);
+    const size_t bytes = (size_t)n16 * 16;
+    void* in[5] = {};
+    void* out[2] = {};
+    int rc = HB_OK;
+    for (int k = 0; k < nin && rc == HB_OK; ++k)
+        if (hipMalloc(&in[k], bytes) != hipSuccess) rc = fail(HB_E_NOMEM, "probe allocation");
+    for (int k = 0; k < nout && rc == HB_OK; ++k)
+        if (hipMalloc(&out[k], bytes) != hipSuccess) rc = fail(HB_E_NOMEM, "probe allocation");
+    for (int k = 0; k < nin && rc == HB_OK; ++k)
+        if (hipMemset(in[k], 0, bytes) != hipSuccess) rc = fail(HB_E_HIP, "probe memset");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == HB_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(HB_E_HIP, "probe events");
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long want = (n16 + 255) / 256;
+    const int blocks = (int)std::min<long long>(want, (long long)cus * 16);
+    if (rc == HB_OK) rc = from_hip(launch_probe(kind, in, out, n16, blocks, nullptr), "probe");
+    if (rc == HB_OK) rc = from_hip(hipEventRecord(e0, nullptr), "event");
+    for (int i = 0; i < iters && rc == HB_OK; ++i)
+        rc = from_hip(launch_probe(kind, in, out, n16, blocks, nullptr), "probe");
+    if (rc == HB_OK) rc = from_hip(hipEventRecord(e1, nullptr), "event");
+    if (rc == HB_OK) rc = from_hip(hipEventSynchronize(e1), "event sync");
+    float ms = 0;
+    if (rc == HB_OK) rc = from_hip(hipEventElapsedTime(&ms, e0, e1), "event elapsed");
+    if (rc == HB_OK) *gbps = (double)bytes * (nin + nout) * iters / (ms * 1e-3) / 1e9;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* p : in)
+        if (p) (void)hipFree(p);
+    for (void* p : out)
+        if (p) (void)hipFree(p);
+    return rc;
+}

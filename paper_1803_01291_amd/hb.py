@@ -23,7 +23,7 @@ HB_E_ARG, HB_E_CFL, HB_E_NOMEM, HB_E_HIP, HB_E_STATE, HB_E_BUSY, HB_E_NONFINITE 
 HB_F64, HB_F32C = 0, 1
 HB_HOST, HB_DEVICE = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
-HB_ALLOW_UNSTABLE, HB_USE_GRAPH = 1, 2
+HB_ALLOW_UNSTABLE, HB_USE_GRAPH, HB_STAGEWISE = 1, 2, 4
 
 _NAMES = {HB_E_ARG: "HB_E_ARG", HB_E_CFL: "HB_E_CFL", HB_E_NOMEM: "HB_E_NOMEM",
           HB_E_HIP: "HB_E_HIP", HB_E_STATE: "HB_E_STATE", HB_E_BUSY: "HB_E_BUSY",
@@ -89,6 +89,7 @@ _SIGS = {
     "hb_pool_read": [_P, _I, _P, _P, _I, _I],
     "hb_pool_release": [_P, _I],
     "hb_pool_destroy": [_P],
+    "hb_probe_bandwidth": [_I, ctypes.c_size_t, _I, ctypes.POINTER(ctypes.c_double)],
 }
 
 
@@ -365,3 +366,9 @@ def solve_host(w, nsteps: Optional[int] = None, precision: int = HB_F64, flags: 
     finally:
         hb_destroy(h)
     return phi, psi
+
+
+def hb_probe_bandwidth(kind: int, bytes_per_array: int, iters: int = 20) -> float:
+    g = ctypes.c_double()
+    _check(load().hb_probe_bandwidth(int(kind), int(bytes_per_array), int(iters), ctypes.byref(g)))
+    return g.value

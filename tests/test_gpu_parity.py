@@ -94,6 +94,22 @@ def test_graph_replay_bitwise(hb):
     np.testing.assert_array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stage_pair_scheme_equals_stagewise_bitwise(hb, precision):
+    w = si.small_case(75, 22, 19, seed=15, steps=11)
+    a = run_gpu(hb, w, precision=precision)
+    b = run_gpu(hb, w, precision=precision, flags=hb.HB_STAGEWISE)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_stagewise_scheme_vs_oracle(hb, oracle_mod):
+    w = si.small_case(70, 21, 13, seed=16, steps=9)
+    g = run_gpu(hb, w, flags=hb.HB_STAGEWISE)
+    r = oracle.solve_workload(w)
+    assert oracle.rel_maxnorm(*g, *r) <= TOL64
+
+
 def test_tiling_does_not_change_results(hb):
     w = si.small_case(90, 30, 33, seed=9, steps=6)
     ref = run_gpu(hb, w, tiling=(8, 0))
