@@ -15,10 +15,19 @@ Prints ONE JSON line.  Extra objects:
   forms         -- the same step rate for the FP32c form (same grid) when
                    --forms is given;
   hbm_probe     -- with --probe, the streamed-bandwidth ceiling measured by
-                   the library's copy and 5-read/2-write probe kernels.
+                   the library's copy and 5-read/2-write probe kernels;
+  batched       -- 64 uneven solves (N ~ U{64..192}^3, 500 steps) in one launch
+                   per stage pair, FP64 and FP32c, vs the same solves run one
+                   by one;
+  served        -- a Poisson request stream (50/s, N in {48..384}^3, 200-2000
+                   steps, FP64/FP32c) through the continuous-batching pool:
+                   p50/p99 latency and solves/s (offered load is far above
+                   capacity, so latency is mostly queueing).
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -61,6 +70,77 @@ def run_gpu(w, precision, steps, warmup, timed_stage_steps):
     return elapsed, [m / timed_stage_steps for m in stage_ms], d
 
 
+def run_batch(count, steps, warmup):
+    """64 uneven solves (N ~ U{64..192}^3) advanced together: one launch per
+    stage pair per precision over a tile table spanning all solves, hipGraph
+    replay of 16-step chunks.  Baseline: the same solves one after another
+    through the single-solve path (also graph-replayed), same GPU."""
+    import torch
+    import synth_inputs as si
+    from paper_1803_01291_amd import hb
+    ws = si.batch_config(count=count, steps=steps)
+    data = [w.initial()[0] for w in ws]
+    pts = sum(w.points for w in ws)
+    out = {"solves": count, "steps": steps, "grid_points": pts,
+           "sizes": [w.n[0] for w in ws]}
+    for prec, name in ((0, "f64"), (1, "f32c")):
+        cfgs = [hb.config_from_workload(w, prec, hb.HB_USE_GRAPH) for w in ws]
+        b = hb.hb_batch_create(cfgs)
+        try:
+            for i in range(count):
+                hb.hb_batch_set_initial(b, i, data[i], None)
+            hb.hb_batch_step(b, warmup)
+            hb.hb_batch_sync(b)
+            t0 = time.perf_counter()
+            hb.hb_batch_step(b, steps)
+            hb.hb_batch_sync(b)
+            tb = time.perf_counter() - t0
+        finally:
+            hb.hb_batch_destroy(b)
+        handles = []
+        try:
+            for i, w in enumerate(ws):
+                h = hb.hb_create(hb.config_from_workload(w, prec, hb.HB_USE_GRAPH))
+                handles.append(h)
+                hb.hb_set_initial(h, data[i], None)
+                hb.hb_step(h, warmup)
+                hb.hb_sync(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for h in handles:
+                hb.hb_step(h, steps)
+                hb.hb_sync(h)
+            ts = time.perf_counter() - t0
+        finally:
+            for h in handles:
+                hb.hb_destroy(h)
+        out[name] = {"seconds": tb, "solves_per_s": count / tb, "pt_updates_per_s": pts * steps / tb,
+                     "sequential_seconds": ts, "speedup_vs_sequential": ts / tb}
+    out["f32c_speedup_vs_f64"] = out["f64"]["seconds"] / out["f32c"]["seconds"]
+    return out
+
+
+def run_serve(count, rate, budget_gb):
+    """Poisson stream of parameter-sweep requests through the continuous-
+    batching pool; payloads (phi0) are generated before the clock starts."""
+    import synth_inputs as si
+    from paper_1803_01291_amd import hb, serve
+    trace = si.serving_trace(count=count, rate=rate)
+    reqs = []
+    for r in trace:
+        prec = hb.HB_F64 if r.precision == "f64" else hb.HB_F32C
+        reqs.append(serve.Request(r.index, r.arrival, hb.config_from_workload(r.workload, prec),
+                                  r.workload.steps, r.workload.phi0(), None))
+    res = serve.serve(reqs, budget_bytes=int(budget_gb * (1 << 30)), max_slots=64, advance_k=25,
+                      keep_results=False)
+    offered = sum(int(np.prod(q.phi0.shape)) * q.steps for q in reqs) / max(trace[-1].arrival, 1e-9)
+    return {"requests": count, "rate_per_s": rate, "budget_GiB": budget_gb,
+            "p50_latency_s": res["p50_latency_s"], "p99_latency_s": res["p99_latency_s"],
+            "solves_per_s": res["solves_per_s"], "pt_updates_per_s": res["pt_updates_per_s"],
+            "offered_pt_updates_per_s": offered, "max_active": res["max_active"],
+            "span_s": res["span_s"]}
+
+
 def cpu_baseline(w, steps):
     import oracle
     p0, p1 = w.initial()
@@ -80,7 +160,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--stage-steps", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", action="store_true")
     ap.add_argument("--probe", action="store_true",
@@ -137,6 +223,10 @@ def main():
         out["hbm_probe"] = {"copy_GBps": hb.hb_probe_bandwidth(0, gib, 20),
                             "read5_write2_GBps": hb.hb_probe_bandwidth(2, gib // 2, 20),
                             "bytes_per_array": [gib, gib // 2]}
+    if not args.no_batch:
+        out["batched"] = run_batch(args.batch_count, args.batch_steps, 16)
+    if not args.no_serve:
+        out["served"] = run_serve(args.serve_count, args.serve_rate, 192.0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -136,9 +136,18 @@ struct Solve {
     int prec() const { return cfg.precision; }
 };
 
-size_t solve_footprint(const hb_config& c) {
+// steps the coefficient table holds when it must cover `need` steps
+long long ctab_capacity(long long need, long long have) {
+    long long cap = std::max<long long>(4096, have);
+    while (cap < need) cap *= 2;
+    return cap;
+}
+
+// device bytes of one solve whose coefficient table covers `steps` steps
+size_t solve_footprint(const hb_config& c, long long steps) {
     const Layout L = plan_layout(c);
-    return field_bytes(L) * (size_t)L.nfields + 4096 * 4 * sizeof(double);
+    return field_bytes(L) * (size_t)L.nfields +
+           (size_t)ctab_capacity(steps, 0) * 4 * sizeof(double);
 }
 
 int solve_alloc(Solve& s, const hb_config& c, hipStream_t stream) {
@@ -177,8 +186,7 @@ void fill_ctab(const hb_config& c, long long n0, long long n1, std::vector<doubl
 int ensure_ctab(Solve& s, long long need, hipStream_t stream, bool* reallocated) {
     if (reallocated) *reallocated = false;
     if (need <= s.ctab_steps) return HB_OK;
-    long long cap = std::max<long long>(4096, s.ctab_steps);
-    while (cap < need) cap *= 2;
+    const long long cap = ctab_capacity(need, s.ctab_steps);
     std::vector<double> host;
     fill_ctab(s.cfg, 0, cap, host);
     double* nt = nullptr;
@@ -534,7 +542,7 @@ size_t hb_footprint(const hb_config* cfg) {
     hb_config c = *cfg;
     c.flags |= HB_ALLOW_UNSTABLE;
     if (validate(&c) != HB_OK) return 0;
-    return solve_footprint(c);
+    return solve_footprint(c, 4096);
 }
 
 int hb_create(const hb_config* cfg, hb_solver** out) {
@@ -999,7 +1007,7 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
     HB_TRY(validate(cfg));
     if (!phi0) return fail(HB_E_ARG, "phi0 is NULL");
     if (steps < 0) return fail(HB_E_ARG, "steps must be >= 0");
-    const size_t need = solve_footprint(*cfg) + (size_t)std::max<long long>(steps, 4096) * 32;
+    const size_t need = solve_footprint(*cfg, steps + 1);
     int free_slot = -1;
     for (size_t i = 0; i < p->slots.size(); ++i)
         if (!p->slots[i].busy) {

@@ -1,0 +1,178 @@
+"""Batched and served forms against the single-solve path and the oracle.
+
+The per-point arithmetic does not depend on which launch or tile a point
+falls in, so every solve in a batch or in the serving pool must be bitwise
+equal to the same solve run alone (FP64 and FP32c), whatever else shares
+the launch; a subset is also checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_workloads():
+    ws = [
+        si.small_case(70, 21, 13, seed=21, steps=9),
+        si.small_case(33, 40, 17, seed=22, steps=9, mu2=0.7, lam=3.0),
+        si.small_case(130, 9, 24, seed=23, steps=9, inv_L2=0.5, t0=0.2),
+        si.small_case(64, 64, 8, seed=24, steps=9, dt=0.004),
+        si.small_case(5, 6, 7, seed=25, steps=9),
+    ]
+    return ws
+
+
+def alone(hb, w, precision, steps):
+    return hb.solve_host(w, steps, precision=precision)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_bitwise_equals_alone(hb, graph):
+    ws = mixed_workloads()
+    precs = [0, 1, 0, 1, 0]
+    flags = hb.HB_USE_GRAPH if graph else 0
+    cfgs = [hb.config_from_workload(w, p, flags) for w, p in zip(ws, precs)]
+    b = hb.hb_batch_create(cfgs)
+    try:
+        for i, w in enumerate(ws):
+            hb.hb_batch_set_initial(b, i, *w.initial())
+        hb.hb_batch_step(b, 20)
+        hb.hb_batch_step(b, 17)
+        outs = []
+        for i, w in enumerate(ws):
+            p0, _ = w.initial()
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_batch_read(b, i, phi, psi)
+            outs.append((phi, psi))
+    finally:
+        hb.hb_batch_destroy(b)
+    for (phi, psi), w, p in zip(outs, ws, precs):
+        ref = alone(hb, w, p, 37)
+        np.testing.assert_array_equal(phi, ref[0])
+        np.testing.assert_array_equal(psi, ref[1])
+
+
+def test_batch_vs_oracle(hb, oracle_mod):
+    ws = mixed_workloads()[:3]
+    cfgs = [hb.config_from_workload(w) for w in ws]
+    b = hb.hb_batch_create(cfgs)
+    try:
+        for i, w in enumerate(ws):
+            hb.hb_batch_set_initial(b, i, *w.initial())
+        hb.hb_batch_step(b, 9)
+        for i, w in enumerate(ws):
+            p0, _ = w.initial()
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_batch_read(b, i, phi, psi)
+            r = oracle.solve_workload(w)
+            assert oracle.rel_maxnorm(phi, psi, *r) <= 1e-12
+    finally:
+        hb.hb_batch_destroy(b)
+
+
+def test_pool_mix_bitwise_equals_alone(hb):
+    """Continuous batching: solves join while others are mid-flight, finish
+    at their own step counts, and free their slots for queued ones."""
+    ws = mixed_workloads()
+    steps = [13, 29, 7, 21, 16]
+    precs = [0, 1, 1, 0, 0]
+    budget = 0
+    for w, p in zip(ws, precs):
+        budget = max(budget, hb.hb_footprint(hb.config_from_workload(w, p)))
+    # room for about three solves at once -> admissions must wait for releases
+    pool = hb.hb_pool_create(3 * budget + (1 << 20), 4)
+    results = {}
+    try:
+        queue = list(range(len(ws)))
+        slot_of = {}
+        rounds = 0
+        while queue or slot_of:
+            while queue:
+                i = queue[0]
+                cfg = hb.config_from_workload(ws[i], precs[i])
+                s = hb.hb_pool_admit(pool, cfg, *ws[i].initial(), steps[i])
+                if s is None:
+                    break
+                slot_of[s] = i
+                queue.pop(0)
+            hb.hb_pool_advance(pool, 5)
+            for s in hb.hb_pool_poll(pool):
+                i = slot_of.pop(s)
+                p0, _ = ws[i].initial()
+                phi, psi = np.empty_like(p0), np.empty_like(p0)
+                hb.hb_pool_read(pool, s, phi, psi)
+                hb.hb_pool_release(pool, s)
+                results[i] = (phi, psi)
+            rounds += 1
+            assert rounds < 100
+        active, in_use = hb.hb_pool_stats(pool)
+        assert active == 0 and in_use == 0
+    finally:
+        hb.hb_pool_destroy(pool)
+    for i, w in enumerate(ws):
+        ref = alone(hb, w, precs[i], steps[i])
+        np.testing.assert_array_equal(results[i][0], ref[0])
+        np.testing.assert_array_equal(results[i][1], ref[1])
+
+
+def test_pool_admission_by_footprint(hb):
+    w = si.small_case(64, 32, 32, seed=31, steps=4)
+    cfg = hb.config_from_workload(w)
+    fp = hb.hb_footprint(cfg)
+    pool = hb.hb_pool_create(fp + fp // 2, 8)
+    try:
+        p0, p1 = w.initial()
+        s0 = hb.hb_pool_admit(pool, cfg, p0, p1, 4)
+        assert s0 is not None
+        assert hb.hb_pool_admit(pool, cfg, p0, p1, 4) is None  # over budget: HB_E_BUSY
+        hb.hb_pool_advance(pool, 10)
+        assert hb.hb_pool_poll(pool) == [s0]
+        hb.hb_pool_release(pool, s0)
+        assert hb.hb_pool_admit(pool, cfg, p0, p1, 4) is not None
+    finally:
+        hb.hb_pool_destroy(pool)
+
+
+def test_autotune_restores_state_bitwise(hb):
+    w = si.small_case(96, 40, 30, seed=32, steps=6)
+    p0, p1 = w.initial()
+    ref = hb.solve_host(w, 6)
+    h = hb.hb_create(hb.config_from_workload(w))
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, 2)
+        by, zc = hb.hb_autotune(h, 2)
+        assert by in (8, 16) and zc >= 0
+        assert hb.hb_time(h)[1] == 2
+        hb.hb_step(h, 4)
+        phi, psi = np.empty_like(p0), np.empty_like(p0)
+        hb.hb_read(h, phi, psi)
+    finally:
+        hb.hb_destroy(h)
+    np.testing.assert_array_equal(phi, ref[0])
+    np.testing.assert_array_equal(psi, ref[1])
+
+
+def test_serving_loop_results_equal_alone(hb):
+    """The request loop: staggered arrivals overlap on the device; each
+    result equals the same solve run alone (bitwise)."""
+    from paper_1803_01291_amd import serve
+    ws = mixed_workloads()
+    steps = [31, 12, 25, 18, 40]
+    precs = [1, 0, 0, 1, 0]
+    reqs = []
+    for i, w in enumerate(ws):
+        p0, p1 = w.initial()
+        arrival = 0.0 if i < 2 else 0.001 * i  # two at once, the rest staggered
+        reqs.append(serve.Request(i, arrival, hb.config_from_workload(w, precs[i]), steps[i], p0, p1))
+    budget = sum(hb.hb_footprint(r.cfg) for r in reqs)
+    out = serve.serve(reqs, budget_bytes=budget // 2, max_slots=3, advance_k=4)
+    assert len(out["completions"]) == len(ws)
+    assert out["max_active"] >= 2
+    for c in out["completions"]:
+        ref = alone(hb, ws[c.index], precs[c.index], steps[c.index])
+        np.testing.assert_array_equal(c.phi, ref[0])
+        np.testing.assert_array_equal(c.psi, ref[1])
