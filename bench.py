@@ -45,6 +45,20 @@ KERNEL_BYTES = {0: [32, 48], 1: [16, 40]}
 # the per-stage (19-pass) scheme: 3, 4, 5, 7 passes; FP32c + 16 B in stage 4
 STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 
+# HBM bytes per launch of the FP64 stage-pair kernels on the 256^3 workload,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (profiles/
+# pair_kernels_cube256.md), each scaled by the counter's reading for the
+# plain copy probe of known size.  Valid only for the kernel source they were
+# measured on; any other source reports traffic null.
+TRAFFIC_KERNEL_SHA = "1c864f3fc00eddd9"
+TRAFFIC_BYTES_F64 = [569.6 * 2 ** 20, 984.8 * 2 ** 20]
+
+
+def kernel_source_sha():
+    import hashlib
+    p = os.path.join(ROOT, "paper_1803_01291_amd", "csrc", "hb_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
 
 def run_gpu(w, precision, steps, warmup, timed_stage_steps):
     import numpy as np
@@ -204,7 +218,10 @@ def main():
                                f"8 seeded Gaussians, dt=0.005, FP64",
                    "grid": [args.n] * 3, "dt": w.dt, "precision": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (TRAFFIC_BYTES_F64[dom]
+                                 if kernel_source_sha() == TRAFFIC_KERNEL_SHA and args.n == 256
+                                 else None),
                      "kernel": ["pair_kernel stages 1+2", "pair_kernel stages 3+4"][dom],
                      "kernel_ms": stage_ms,
                      "bytes_per_point": KERNEL_BYTES[0],
