@@ -2,14 +2,18 @@
 
 Workload: 256^3 interior points on [-16,16]^3 (h = 0.125), mu^2 = 2,
 lambda = 1, phi0 = 8 seeded Gaussians (seed 0), phi1 = 0, dt = 0.005 (the
-2000-step single-solve configuration).  A "step" is one full RK4 step (2 fused
-stage-pair kernels + the step-counter tick) over the whole grid; inputs are
+2000-step single-solve configuration).  A "step" is one full RK4 step (one
+whole-step kernel + the step-counter tick) over the whole grid; inputs are
 resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      -- dominant kernel (stage pair 3+4: 6 field passes = 48 B/point
-                   FP64) algorithmic bytes / its average duration, from HIP
-                   events on the solver's stream, against 8 TB/s;
+  roofline      -- the whole-step kernel (one launch per RK4 step): the
+                   contract's algorithmic bytes per point-step (152 B FP64,
+                   the 19 field passes of one-pass-per-stage RK4) x points /
+                   the kernel's mean duration from HIP events on the solver's
+                   stream, against 8 TB/s.  The kernel itself moves only
+                   32 B/point (Y in, Y' out): own_GBps/own_frac price that;
+                   traffic is the PMC-measured bytes per launch;
   cpu_baseline  -- the FP64 CPU oracle on a bounded number of steps of the
                    same grid, on this host's cores;
   forms         -- the same step rate for the FP32c form (same grid) when
@@ -41,17 +45,20 @@ HBM_PEAK_GBS = 8000.0
 # reads Y_phi, Y_psi and writes G1, G2 (4 passes); kernel B (stages 3+4)
 # reads Y_phi, Y_psi, G1, G2 and writes Y'_phi, Y'_psi (6 passes); FP32c adds
 # the read and write of the two FP32 low parts in kernel B (16 B).
-KERNEL_BYTES = {0: [32, 48], 1: [16, 40]}
+KERNEL_BYTES = {0: [32, 48], 1: [16, 40]}  # stage-pair kernels (HB_PAIRWISE)
+# whole-step kernel: Y_phi, Y_psi in, Y'_phi, Y'_psi out (+ FP32c low parts
+# read and written: 16 B)
+STEP_BYTES = {0: 32, 1: 32}
 # the per-stage (19-pass) scheme: 3, 4, 5, 7 passes; FP32c + 16 B in stage 4
 STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 
-# HBM bytes per launch of the FP64 stage-pair kernels on the 256^3 workload,
+# HBM bytes per launch of the FP64 whole-step kernel on the 256^3 workload,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (profiles/
-# pair_kernels_cube256.md), each scaled by the counter's reading for the
-# plain copy probe of known size.  Valid only for the kernel source they were
-# measured on; any other source reports traffic null.
-TRAFFIC_KERNEL_SHA = "1c864f3fc00eddd9"
-TRAFFIC_BYTES_F64 = [569.6 * 2 ** 20, 984.8 * 2 ** 20]
+# step_kernel_cube256.md), each scaled by the counter's reading for the plain
+# copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
+# kernel source they were measured on; any other source reports null.
+TRAFFIC_KERNEL_SHA = "3b782f75fab88eea"
+TRAFFIC_BYTES_F64 = 647.7 * 2 ** 20
 
 
 def kernel_source_sha():
@@ -195,12 +202,13 @@ def main():
     w = si.config2(n=args.n)
     N = w.points
     elapsed, stage_ms, diag = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps)
-    stage_ms = stage_ms[:2]
+    kernel_ms = stage_ms[0]          # one whole-step kernel per step
     rate = N * args.steps / elapsed
-    dom = max(range(2), key=lambda s: stage_ms[s])
-    dom_bytes = KERNEL_BYTES[0][dom] * N
-    achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
-    step_alg = sum(KERNEL_BYTES[0]) * N
+    # algorithmic bytes per launch: the per-point-step figure of the
+    # measurement contract (152 B FP64 = 19 field passes) x interior points
+    achieved = sum(STAGEWISE_BYTES[0]) * N / (kernel_ms * 1e-3) / 1e9
+    own = STEP_BYTES[0] * N / (kernel_ms * 1e-3) / 1e9
+    step_alg = sum(STAGEWISE_BYTES[0]) * N
     out = {
         "metric": "RK4 grid-point updates/s (FP64, fused 13-point stencil stages)",
         "value": rate,
@@ -219,12 +227,14 @@ def main():
                    "grid": [args.n] * 3, "dt": w.dt, "precision": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (TRAFFIC_BYTES_F64[dom]
+                     "traffic": (TRAFFIC_BYTES_F64
                                  if kernel_source_sha() == TRAFFIC_KERNEL_SHA and args.n == 256
                                  else None),
-                     "kernel": ["pair_kernel stages 1+2", "pair_kernel stages 3+4"][dom],
-                     "kernel_ms": stage_ms,
-                     "bytes_per_point": KERNEL_BYTES[0],
+                     "kernel": "step_kernel (whole RK4 step)",
+                     "kernel_ms": kernel_ms,
+                     "bytes_per_point": sum(STAGEWISE_BYTES[0]),
+                     "own_bytes_per_point": STEP_BYTES[0],
+                     "own_GBps": own, "own_frac": own / HBM_PEAK_GBS,
                      "step_alg_GBps": step_alg / (elapsed / args.steps) / 1e9,
                      "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
@@ -232,8 +242,9 @@ def main():
     if args.forms:
         e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
-                                 "kernel_ms": ms32[:2],
-                                 "step_alg_GBps": sum(KERNEL_BYTES[1]) * N / (e32 / args.steps) / 1e9}}
+                                 "kernel_ms": ms32[0],
+                                 "alg_GBps": sum(STAGEWISE_BYTES[1]) * N / (ms32[0] * 1e-3) / 1e9,
+                                 "own_GBps": STEP_BYTES[1] * N / (ms32[0] * 1e-3) / 1e9}}
     if args.probe:
         from paper_1803_01291_amd import hb
         gib = 1 << 30

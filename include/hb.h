@@ -65,8 +65,10 @@ extern "C" {
 #define HB_ALLOW_UNSTABLE 1u /* skip the dt stability check                    */
 #define HB_USE_GRAPH 2u      /* replay captured hipGraphs of several steps     */
 #define HB_STAGEWISE 4u      /* one launch per RK4 stage (19 field passes per  */
-                             /* step) instead of the default stage-pair       */
-                             /* launches (10 passes); bitwise-equal results   */
+                             /* step); bitwise-equal results                  */
+#define HB_PAIRWISE 8u       /* one launch per stage pair (10 passes per step) */
+                             /* instead of the default whole-step launch (4   */
+                             /* passes); bitwise-equal results                */
 
 typedef struct hb_config {
     int32_t n[3];        /* interior points along x, y, z (each >= 1)              */
@@ -121,15 +123,17 @@ int hb_set_initial(hb_solver* s, const void* phi0, const void* phi1, int mem, in
 int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int mem, int dtype);
 
 /* Enqueue nsteps RK4 steps on the solver's stream and return without waiting.
- * Each step is 2 fused stage-pair kernels (stages 1+2, then 3+4), or 4
- * per-stage kernels with HB_STAGEWISE, plus a tiny step-counter kernel.
- * HB_E_STATE before initial data. */
+ * Each step is one whole-step kernel (default), 2 stage-pair kernels
+ * (HB_PAIRWISE) or 4 per-stage kernels (HB_STAGEWISE); a tiny kernel advances
+ * the device step counter after each batch of steps.  HB_E_STATE before
+ * initial data. */
 int hb_step(hb_solver* s, int64_t nsteps);
 
 /* Like hb_step, but waits after every step and returns the summed device time
  * of each kernel of the step in stage_ms[0..3] (HIP events on the solver's
- * stream around each launch): the 2 stage-pair kernels in [0..1] (with [2..3]
- * zero), or the 4 per-stage kernels with HB_STAGEWISE.  For measurement. */
+ * stream around each launch): the whole-step kernel in [0], the 2 stage-pair
+ * kernels in [0..1] (HB_PAIRWISE) or the 4 per-stage kernels (HB_STAGEWISE);
+ * unused entries are 0.  For measurement. */
 int hb_step_timed(hb_solver* s, int64_t nsteps, double* stage_ms);
 
 /* Wait for the solver's stream, then copy the interior state out.  Either
@@ -146,8 +150,11 @@ int hb_sync(hb_solver* s);
  * HB_E_NONFINITE (with *out filled) when the state holds NaN/Inf. */
 int hb_diagnostics(hb_solver* s, hb_diag* out);
 
-/* Tile shape of the stage kernels: by in {8, 16} rows of 64 columns, zc >= 1
- * planes per tile (0 = library default).  Results do not depend on it. */
+/* Tile shape: zc >= 1 planes per tile (0 = library default); by in {8, 16}:
+ * rows of 64 columns per tile for the stage-pair and per-stage kernels
+ * (default 16); for the whole-step kernel by = 8 selects 28 x 12 tiles
+ * (512-thread blocks, two per CU; the default) and by = 16 selects 60 x 12
+ * tiles (1024-thread blocks).  Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 
 /* Time every candidate tile shape for `trial_steps` steps on the current

@@ -51,6 +51,12 @@ int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile
 // (writes the next state).  Bitwise equal to the four per-stage launches.
 int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream);
+// Whole-step kernel: one launch per RK4 step.  `width` (64 or 32) is the
+// x-extent of the region a block's threads own; its tiles are (width - 4) x
+// STEP_TILE_Y interior columns.  Bitwise equal to the stage-pair kernels.
+constexpr int STEP_TILE_Y = 12;
+int launch_step(int prec, int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                long long kstep, void* stream);
 int launch_tick(SolveDesc* descs, int count, long long k, void* stream);
 int launch_set_target(SolveDesc* descs, int index, long long target, void* stream);
 int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream);

@@ -34,6 +34,8 @@
 // HBM bandwidth.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hb_internal.h"
 
 namespace hb {
@@ -48,9 +50,21 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x * q + min(x, r) + l;
 }
 
+// Field pointers come from the descriptor, so the compiler cannot see that
+// they address global memory and would emit flat accesses (which also count
+// against the LDS wait counter and serialise prefetches with LDS traffic).
+// All field accesses go through explicit global-address-space pointers.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
 template <typename T>
 __device__ __forceinline__ T ldg(const T* __restrict__ p, long long off, bool ok) {
-    return ok ? p[off] : T(0);
+    return ok ? ((gptr<const T>)p)[off] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void stg(T* p, long long off, T v) {
+    ((gptr<T>)p)[off] = v;
 }
 
 template <typename T, int STAGE, bool COMP>
@@ -83,7 +97,7 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
     const long long sy = d->sy, sz = d->sz;
     const int nx = d->nx, ny = d->ny;
 
-    const T c = (T)d->ctab[4 * n + (STAGE - 1)];
+    const T c = (T)ldg(d->ctab, 4 * n + (STAGE - 1), true);
     const T w0 = (T)d->w0;
     const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
     const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
@@ -200,14 +214,14 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
         const long long o = (long long)z * sz + own_off;
         if (own_st) {
             if constexpr (STAGE < 4) {
-                ((T*)d->g[STAGE - 1])[o] = g;
+                stg((T*)d->g[STAGE - 1], o, g);
             } else if constexpr (!COMP) {
                 const double dt6 = d->dt6;
                 const T k2 = r0.s + hdt * r0.g1;
                 const T k3 = r0.s + hdt * r0.g2;
-                ((T*)d->y_phi[par ^ 1])[o] = r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi);
-                ((T*)d->y_psi[par ^ 1])[o] =
-                    r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * r0.g3 + g);
+                stg((T*)d->y_phi[par ^ 1], o, (T)(r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi)));
+                stg((T*)d->y_psi[par ^ 1], o,
+                    (T)(r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * r0.g3 + g)));
             } else {
                 // compensated state: v = hi + lo carried in FP64 registers;
                 // the stage derivatives come from the FP32 stage arithmetic
@@ -219,10 +233,10 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
                 const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
                 const double ns_ = s + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
                 const float hp = (float)np_, hs = (float)ns_;
-                ((float*)d->y_phi[par ^ 1])[o] = hp;
-                ((float*)d->y_psi[par ^ 1])[o] = hs;
-                d->lo_phi[o] = (float)(np_ - (double)hp);
-                d->lo_psi[o] = (float)(ns_ - (double)hs);
+                stg((float*)d->y_phi[par ^ 1], o, hp);
+                stg((float*)d->y_psi[par ^ 1], o, hs);
+                stg(d->lo_phi, o, (float)(np_ - (double)hp));
+                stg(d->lo_psi, o, (float)(ns_ - (double)hs));
             }
         }
         q0 = q1; q1 = q2; q2 = q3; q3 = q4;
@@ -265,8 +279,8 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const long long sy = d->sy, sz = d->sz;
     const int nx = d->nx, ny = d->ny;
 
-    const T ca = (T)d->ctab[4 * n + 2 * PAIR];
-    const T cb = (T)d->ctab[4 * n + 2 * PAIR + 1];
+    const T ca = (T)ldg(d->ctab, 4 * n + 2 * PAIR, true);
+    const T cb = (T)ldg(d->ctab, 4 * n + 2 * PAIR + 1, true);
     const T w0 = (T)d->w0;
     const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
     const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
@@ -385,8 +399,8 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             const T spsi2 = r0.s + hdt * g1;
             const T g2 = -T(3) * spsi2 + cb * lapB + mu2 * SB - lam * SB * SB * SB;
             if (own_st) {
-                ((T*)d->g[0])[o] = g1;
-                ((T*)d->g[1])[o] = g2;
+                stg((T*)d->g[0], o, g1);
+                stg((T*)d->g[1], o, g2);
             }
         } else {
             // stage 3: S_psi,3 = Y_psi + dt/2 G2;  stage 4: S_psi,4 = Y_psi + dt G3
@@ -400,9 +414,10 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                     const double dt6 = d->dt6;
                     const T k2 = r0.s + hdt * r0.g1;
                     const T k3 = r0.s + hdt * r0.g2;
-                    ((T*)d->y_phi[par ^ 1])[o] = r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi4);
-                    ((T*)d->y_psi[par ^ 1])[o] =
-                        r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * g3 + g4);
+                    stg((T*)d->y_phi[par ^ 1], o,
+                        (T)(r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi4)));
+                    stg((T*)d->y_psi[par ^ 1], o,
+                        (T)(r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * g3 + g4)));
                 } else {
                     const double hd = d->hdt, dd = d->dt, dt6 = d->dt6;
                     const double p = (double)r0.p + (double)lp;
@@ -412,10 +427,10 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                     const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
                     const double ns_ = s + dt6 * (e1 + 2.0 * e2 + 2.0 * e3 + e4);
                     const float hp = (float)np_, hs = (float)ns_;
-                    ((float*)d->y_phi[par ^ 1])[o] = hp;
-                    ((float*)d->y_psi[par ^ 1])[o] = hs;
-                    d->lo_phi[o] = (float)(np_ - (double)hp);
-                    d->lo_psi[o] = (float)(ns_ - (double)hs);
+                    stg((float*)d->y_phi[par ^ 1], o, hp);
+                    stg((float*)d->y_psi[par ^ 1], o, hs);
+                    stg(d->lo_phi, o, (float)(np_ - (double)hp));
+                    stg(d->lo_psi, o, (float)(ns_ - (double)hs));
                 }
             }
         }
@@ -425,6 +440,273 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         h0 = hn;
         lp = lpn; ls = lsn;
         buf ^= 1;
+    }
+}
+
+// Whole-step kernel: all four stages of one RK4 step in one z-march.
+// A block owns an interior tile of (RX-4) x 12 columns; its RX*16 threads own
+// the RX x 16 columns of the tile plus a 2-cell ring (region R2).  RX = 64
+// (1024 threads, one block per CU) or 32 (512 threads, two blocks per CU).
+// Per plane zi:
+//   stage 1+2 on R2: G1, G2 at plane zi from the stencils of Y_phi and S_phi,2
+//     (x-y part from an LDS plane over the 4-cell ring R4, z part from each
+//     thread's register queue of Y planes zi-2..zi+2); outside the grid
+//     interior G1 = G2 = 0, exactly the zero halo the two-kernel scheme reads;
+//   S_phi,3 and S_phi,4 at plane zi on R2 go to a 3-plane LDS ring (their
+//     x-y stencil part) and to each thread's register queue (z part);
+//   stage 3+4 and the update at plane z = zi - 2 on the tile, from the ring,
+//     the queues and the thread's own Y and G1, G2 (2-plane delay).
+// HBM traffic is Y in and Y' out (4 field passes per step); the ring columns'
+// G1, G2 are recomputed by neighbouring blocks instead of stored.  The
+// per-point arithmetic and its order are those of the stage-pair kernels, so
+// results are bitwise equal to them.  One barrier per plane: the stage-1+2
+// plane is double-buffered, and stages 3+4 read ring slots written two
+// planes earlier.  All per-plane queues are rings indexed by the plane number
+// modulo 6 and the loop is unrolled by 6, so queue shifts are register
+// renaming rather than moves.
+constexpr int SK_RY = 16;
+
+// 32-wide blocks: two resident 8-wave blocks per CU = 4 waves per SIMD
+// (the second launch-bounds argument is the minimum waves per SIMD)
+template <typename T, bool COMP, int SK_RX>
+__global__ void __launch_bounds__(SK_RX * SK_RY, SK_RX == 32 ? 4 : 1)
+step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
+            long long kstep) {
+    constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
+    constexpr int SK_NOUTER = SK_QX * SK_QY - SK_RX * SK_RY;
+    static_assert(SK_NOUTER <= SK_RX * SK_RY, "one outer-ring column per thread at most");
+    __shared__ T pa[2][SK_QY][SK_QX];      // Y_phi at plane zi over R4 (double-buffered)
+    __shared__ T pb[2][SK_QY][SK_QX];      // S_phi,2 at plane zi over R4
+    __shared__ T r3[3][SK_RY][SK_RX];      // S_phi,3 at planes zi-2..zi over R2
+    __shared__ T r4[3][SK_RY][SK_RX];      // S_phi,4
+
+    const Tile tl = tiles[xcd_remap(blockIdx.x, ntiles)];
+    const SolveDesc* __restrict__ d = descs + tl.solve;
+    const long long n = d->nstep + kstep;
+    if (n >= d->target) return;  // uniform over the block
+    const int par = (int)(n & 1);
+
+    const T* __restrict__ Yp = (const T*)d->y_phi[par];
+    const T* __restrict__ Ys = (const T*)d->y_psi[par];
+    T* __restrict__ Op = (T*)d->y_phi[par ^ 1];
+    T* __restrict__ Os = (T*)d->y_psi[par ^ 1];
+    const long long sy = d->sy, sz = d->sz;
+    const int nx = d->nx, ny = d->ny, nz = d->nz;
+
+    const T c1 = (T)ldg(d->ctab, 4 * n + 0, true), c2 = (T)ldg(d->ctab, 4 * n + 1, true);
+    const T c3 = (T)ldg(d->ctab, 4 * n + 2, true), c4 = (T)ldg(d->ctab, 4 * n + 3, true);
+    const T w0 = (T)d->w0;
+    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
+    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
+    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
+    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+    const double dt6 = d->dt6, hdd = d->hdt, dtd = d->dt;
+
+    const int tid = threadIdx.x;
+    const int rx = tid % SK_RX, ry = tid / SK_RX;
+    const int gx = tl.x0 - 2 + rx, gy = tl.y0 - 2 + ry;
+    const bool col_ld = (gx >= -2) && (gx < nx + 2) && (gy >= -2) && (gy < ny + 2);
+    const bool col_int = (gx >= 0) && (gx < nx) && (gy >= 0) && (gy < ny);
+    const bool core = (rx >= 2) && (rx < SK_RX - 2) && (ry >= 2) && (ry < SK_RY - 2);
+    const bool own_st = core && col_int;
+    const long long col_off = (long long)gy * sy + gx;
+
+    // outer ring (R4 minus R2): rows 0,1 and QY-2,QY-1 of R4, then columns
+    // 0,1 and QX-2,QX-1 of the middle rows
+    bool has_outer = false, outer_ld = false;
+    int ox = 0, oy = 0;
+    long long outer_off = 0;
+    if (tid < SK_NOUTER) {
+        if (tid < 4 * SK_QX) {
+            const int r = tid / SK_QX;
+            oy = (r < 2) ? r : SK_QY - 4 + r;
+            ox = tid % SK_QX;
+        } else {
+            const int h = tid - 4 * SK_QX;
+            const int k = h & 3;
+            oy = 2 + (h >> 2);
+            ox = (k < 2) ? k : SK_QX - 4 + k;
+        }
+        has_outer = true;
+        const int hx = tl.x0 - 4 + ox, hy = tl.y0 - 4 + oy;
+        outer_ld = (hx >= -2) && (hx < nx + 2) && (hy >= -2) && (hy < ny + 2);
+        outer_off = (long long)hy * sy + hx;
+    }
+
+    auto plane_ok = [&](int p) { return p >= -2 && p < nz + 2; };
+
+    const int z0 = tl.z0, z1 = tl.z1;
+    const int zbase = z0 - 2;           // first plane of stages 1+2
+    const int niter = z1 - z0 + 4;      // planes zbase .. z1+1
+    const int zlast = z1 + 3;           // highest plane any stage-1+2 evaluation reads
+
+    // rings indexed by (plane - zbase + 6) % 6 (+6: planes down to zbase-2)
+    T qp[6], qs[6];        // Y_phi, Y_psi of the own column
+    T a3q[6], a4q[6];      // own-column S_phi,3 and S_phi,4
+    T g1r[6], g2r[6];      // own-column G1, G2
+    T opr[2], osr[2];      // outer-ring Y, by plane parity
+    float lpr[2], lsr[2];  // FP32c low parts, by output-plane parity
+    for (int k = 0; k < 6; ++k) {
+        qp[k] = qs[k] = a3q[k] = a4q[k] = g1r[k] = g2r[k] = T(0);
+    }
+    opr[0] = opr[1] = osr[0] = osr[1] = T(0);
+    lpr[0] = lpr[1] = lsr[0] = lsr[1] = 0.f;
+    // prologue: own Y at planes zbase-2 .. zbase+2, outer ring at plane zbase
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int p = zbase - 2 + k;
+        const bool ok = col_ld && plane_ok(p);
+        const long long o = (long long)p * sz + col_off;
+        qp[(k + 4) % 6] = ldg(Yp, o, ok);
+        qs[(k + 4) % 6] = ldg(Ys, o, ok);
+    }
+    {
+        const bool ok = has_outer && outer_ld && plane_ok(zbase);
+        opr[0] = ldg(Yp, (long long)zbase * sz + outer_off, ok);
+        osr[0] = ldg(Ys, (long long)zbase * sz + outer_off, ok);
+    }
+
+    // one plane; PH = (zi - zbase) % 6 is a compile-time constant
+    auto plane = [&](auto ph, int it) {
+        constexpr int PH = decltype(ph)::value;
+        constexpr int B = PH & 1;                    // LDS double buffer
+        constexpr int RS = PH % 3;                   // LDS ring slot of plane zi
+        constexpr int RS2 = (PH + 1) % 3;            // ... of plane zi - 2
+        auto Q = [](int k) { return (PH + 6 + k) % 6; };  // ring slot of plane zi + k
+        const int zi = zbase + it;
+
+        // prefetch: own Y at plane zi+3, outer ring at plane zi+1, FP32c low
+        // parts at the next output plane zi-1
+        {
+            const int p = zi + 3;
+            if (p <= zlast) {
+                const bool ok = col_ld && plane_ok(p);
+                const long long o = (long long)p * sz + col_off;
+                qp[Q(3)] = ldg(Yp, o, ok);
+                qs[Q(3)] = ldg(Ys, o, ok);
+            }
+            const int q = zi + 1;
+            if (q <= z1 + 1) {
+                const bool ok = has_outer && outer_ld && plane_ok(q);
+                opr[B ^ 1] = ldg(Yp, (long long)q * sz + outer_off, ok);
+                osr[B ^ 1] = ldg(Ys, (long long)q * sz + outer_off, ok);
+            }
+            if constexpr (COMP) {
+                const int zz = zi - 1;
+                if (zz >= z0 && zz < z1) {
+                    const long long o = (long long)zz * sz + col_off;
+                    lpr[B ^ 1] = ldg(d->lo_phi, o, own_st);
+                    lsr[B ^ 1] = ldg(d->lo_psi, o, own_st);
+                }
+            }
+        }
+
+        // ---- stages 1 + 2 at plane zi over R2 ----
+        const T yp0 = qp[Q(0)], ys0 = qs[Q(0)];
+        pa[B][ry + 2][rx + 2] = yp0;
+        pb[B][ry + 2][rx + 2] = yp0 + hdt * ys0;
+        if (has_outer) {
+            pa[B][oy][ox] = opr[B];
+            pb[B][oy][ox] = opr[B] + hdt * osr[B];
+        }
+        // the only barrier of the plane: it publishes this plane's stage-1+2
+        // inputs and the ring slot written two planes ago (read below)
+        __syncthreads();
+
+        T g1 = T(0), g2 = T(0);
+        if (col_int && zi >= 0 && zi < nz) {
+            const int lx = rx + 2, ly = ry + 2;
+            const T(*A)[SK_QX] = pa[B];
+            const T(*Bp)[SK_QX] = pb[B];
+            const T SA = yp0, SB = yp0 + hdt * ys0;
+            T lapA = w0 * SA;
+            lapA += w1x * (A[ly][lx - 1] + A[ly][lx + 1]);
+            lapA += w2x * (A[ly][lx - 2] + A[ly][lx + 2]);
+            lapA += w1y * (A[ly - 1][lx] + A[ly + 1][lx]);
+            lapA += w2y * (A[ly - 2][lx] + A[ly + 2][lx]);
+            lapA += w1z * (qp[Q(-1)] + qp[Q(1)]);
+            lapA += w2z * (qp[Q(-2)] + qp[Q(2)]);
+            T lapB = w0 * SB;
+            lapB += w1x * (Bp[ly][lx - 1] + Bp[ly][lx + 1]);
+            lapB += w2x * (Bp[ly][lx - 2] + Bp[ly][lx + 2]);
+            lapB += w1y * (Bp[ly - 1][lx] + Bp[ly + 1][lx]);
+            lapB += w2y * (Bp[ly - 2][lx] + Bp[ly + 2][lx]);
+            lapB += w1z * ((qp[Q(-1)] + hdt * qs[Q(-1)]) + (qp[Q(1)] + hdt * qs[Q(1)]));
+            lapB += w2z * ((qp[Q(-2)] + hdt * qs[Q(-2)]) + (qp[Q(2)] + hdt * qs[Q(2)]));
+            g1 = -T(3) * ys0 + c1 * lapA + mu2 * SA - lam * SA * SA * SA;
+            const T spsi2 = ys0 + hdt * g1;
+            g2 = -T(3) * spsi2 + c2 * lapB + mu2 * SB - lam * SB * SB * SB;
+        }
+        // stage inputs of stages 3 and 4 at plane zi (zero outside the grid)
+        const T s3 = yp0 + hdt * (ys0 + hdt * g1);
+        const T s4 = yp0 + dtT * (ys0 + hdt * g2);
+        a3q[Q(0)] = s3;
+        a4q[Q(0)] = s4;
+        g1r[Q(0)] = g1;
+        g2r[Q(0)] = g2;
+        r3[RS][ry][rx] = s3;
+        r4[RS][ry][rx] = s4;
+
+        // ---- stages 3 + 4 and the update at plane z = zi - 2 on the tile ----
+        const int z = zi - 2;
+        if (z >= z0 && own_st) {
+            const T SA = a3q[Q(-2)], SB = a4q[Q(-2)];
+            T lapA = w0 * SA;
+            lapA += w1x * (r3[RS2][ry][rx - 1] + r3[RS2][ry][rx + 1]);
+            lapA += w2x * (r3[RS2][ry][rx - 2] + r3[RS2][ry][rx + 2]);
+            lapA += w1y * (r3[RS2][ry - 1][rx] + r3[RS2][ry + 1][rx]);
+            lapA += w2y * (r3[RS2][ry - 2][rx] + r3[RS2][ry + 2][rx]);
+            lapA += w1z * (a3q[Q(-3)] + a3q[Q(-1)]);
+            lapA += w2z * (a3q[Q(-4)] + a3q[Q(0)]);
+            T lapB = w0 * SB;
+            lapB += w1x * (r4[RS2][ry][rx - 1] + r4[RS2][ry][rx + 1]);
+            lapB += w2x * (r4[RS2][ry][rx - 2] + r4[RS2][ry][rx + 2]);
+            lapB += w1y * (r4[RS2][ry - 1][rx] + r4[RS2][ry + 1][rx]);
+            lapB += w2y * (r4[RS2][ry - 2][rx] + r4[RS2][ry + 2][rx]);
+            lapB += w1z * (a4q[Q(-3)] + a4q[Q(-1)]);
+            lapB += w2z * (a4q[Q(-4)] + a4q[Q(0)]);
+            const T yp = qp[Q(-2)], ys = qs[Q(-2)], e1 = g1r[Q(-2)], e2 = g2r[Q(-2)];
+            const T spsi3 = ys + hdt * e2;
+            const T g3 = -T(3) * spsi3 + c3 * lapA + mu2 * SA - lam * SA * SA * SA;
+            const T spsi4 = ys + dtT * g3;
+            const T g4 = -T(3) * spsi4 + c4 * lapB + mu2 * SB - lam * SB * SB * SB;
+            const long long o = (long long)z * sz + col_off;
+            if constexpr (!COMP) {
+                const T k2 = ys + hdt * e1;
+                const T k3 = ys + hdt * e2;
+                stg(Op, o, (T)(yp + dt6 * (ys + T(2) * k2 + T(2) * k3 + spsi4)));
+                stg(Os, o, (T)(ys + dt6 * (e1 + T(2) * e2 + T(2) * g3 + g4)));
+            } else {
+                const double pp = (double)yp + (double)lpr[B];
+                const double ss = (double)ys + (double)lsr[B];
+                const double a1 = e1, a2 = e2, a3 = g3, a4 = g4;
+                const double k2 = ss + hdd * a1, k3 = ss + hdd * a2, k4 = ss + dtd * a3;
+                const double vp = pp + dt6 * (ss + 2.0 * k2 + 2.0 * k3 + k4);
+                const double vs = ss + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
+                const float hp = (float)vp, hs = (float)vs;
+                stg((float*)Op, o, hp);
+                stg((float*)Os, o, hs);
+                stg(d->lo_phi, o, (float)(vp - (double)hp));
+                stg(d->lo_psi, o, (float)(vs - (double)hs));
+            }
+        }
+    };
+
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    // niter = z1 - z0 + 4 >= 5 planes; the block-uniform guards keep every
+    // thread on the same sequence of barriers
+    for (int it = 0; it < niter; it += 6) {
+        plane(I0{}, it);
+        if (it + 1 < niter) plane(I1{}, it + 1);
+        if (it + 2 < niter) plane(I2{}, it + 2);
+        if (it + 3 < niter) plane(I3{}, it + 3);
+        if (it + 4 < niter) plane(I4{}, it + 4);
+        if (it + 5 < niter) plane(I5{}, it + 5);
     }
 }
 
@@ -491,8 +773,8 @@ constexpr int DIAG_THREADS = 256;
 
 template <bool COMP>
 __device__ __forceinline__ double fld(const void* hi, const float* lo, long long o) {
-    if constexpr (COMP) return (double)((const float*)hi)[o] + (double)lo[o];
-    return ((const double*)hi)[o];
+    if constexpr (COMP) return (double)ldg((const float*)hi, o, true) + (double)ldg(lo, o, true);
+    return ldg((const double*)hi, o, true);
 }
 
 // One block per (y, z) row group; per-thread partial sums in a fixed order,
@@ -617,6 +899,20 @@ hipError_t launch_pair_t(int pair, const SolveDesc* descs, const Tile* tiles, in
     return hipGetLastError();
 }
 
+template <typename T, bool COMP>
+hipError_t launch_step_t(int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                         long long kstep, hipStream_t s) {
+    if (width == 64)
+        hipLaunchKernelGGL((step_kernel<T, COMP, 64>), dim3(ntiles), dim3(64 * SK_RY), 0, s, descs,
+                           tiles, ntiles, kstep);
+    else if (width == 32)
+        hipLaunchKernelGGL((step_kernel<T, COMP, 32>), dim3(ntiles), dim3(32 * SK_RY), 0, s, descs,
+                           tiles, ntiles, kstep);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
@@ -651,6 +947,16 @@ int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* 
         else if (by == 16) e = launch_pair_t<float, 16, true>(pair, descs, tiles, ntiles, kstep, s);
         else return (int)hipErrorInvalidValue;
     }
+    return (int)e;
+}
+
+int launch_step(int prec, int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                long long kstep, void* stream) {
+    if (ntiles <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = prec == PREC_F64
+                       ? launch_step_t<double, false>(width, descs, tiles, ntiles, kstep, s)
+                       : launch_step_t<float, true>(width, descs, tiles, ntiles, kstep, s);
     return (int)e;
 }
 

@@ -321,9 +321,17 @@ int default_zc(const Layout& L, int by) {
     return (int)std::max<long long>(1, zc);
 }
 
+enum Scheme { SCHEME_STEP = 0, SCHEME_PAIRS = 1, SCHEME_STAGES = 2 };
+
+int scheme_of(uint32_t flags) {
+    if (flags & HB_STAGEWISE) return SCHEME_STAGES;
+    if (flags & HB_PAIRWISE) return SCHEME_PAIRS;
+    return SCHEME_STEP;
+}
+
 struct Group {
     int prec = HB_F64;
-    bool stagewise = false;  // 4 per-stage launches instead of 2 stage-pair launches
+    int scheme = SCHEME_STEP;  // 1 whole-step, 2 stage-pair or 4 per-stage launches per step
     int by = DEFAULT_BY;
     int zc = 0;  // 0 = default per solve
     std::vector<Solve*> members;
@@ -354,14 +362,46 @@ struct Group {
     }
 };
 
-void make_tiles(const Solve& s, int solve_index, int by, int zc_req, std::vector<Tile>& out) {
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// whole-step kernel: region width 64 (by = 16) or 32 (by = 8) columns
+int step_width(int by) { return by == 16 ? 64 : 32; }
+
+// 32-plane z-marches (4 warm-up planes), shorter only while one solve would
+// give fewer tiles than resident block slots; measured best on 256^3
+int default_zc_step(const Layout& L, int by, int nmembers) {
+    if (nmembers > 1) return std::min(L.nz, 32);
+    const int tx = step_width(by) - 4;
+    const long long xy = (long long)((L.nx + tx - 1) / tx) * ((L.ny + STEP_TILE_Y - 1) / STEP_TILE_Y);
+    const long long slots = (long long)device_cus() * (step_width(by) == 32 ? 2 : 1);
+    int zc = std::min(L.nz, 32);
+    while (zc > 8 && xy * ((L.nz + zc - 1) / zc) < slots) zc = (zc + 1) / 2;
+    return zc;
+}
+
+void make_tiles(const Solve& s, int solve_index, int scheme, int by, int zc_req, int nmembers,
+                std::vector<Tile>& out) {
     const Layout& L = s.L;
-    const int zc = zc_req > 0 ? zc_req : default_zc(L, by);
+    const int tx = scheme == SCHEME_STEP ? step_width(by) - 4 : TILE_X;
+    const int ty = scheme == SCHEME_STEP ? STEP_TILE_Y : by;
+    const int zc = zc_req > 0 ? zc_req
+                              : (scheme == SCHEME_STEP ? default_zc_step(L, by, nmembers)
+                                                       : default_zc(L, by));
     // z-chunk major, then y, then x: consecutive tiles are spatial neighbours,
     // and the XCD remap hands each XCD a contiguous run of them
     for (int z0 = 0; z0 < L.nz; z0 += zc)
-        for (int y0 = 0; y0 < L.ny; y0 += by)
-            for (int x0 = 0; x0 < L.nx; x0 += TILE_X) {
+        for (int y0 = 0; y0 < L.ny; y0 += ty)
+            for (int x0 = 0; x0 < L.nx; x0 += tx) {
                 Tile t;
                 std::memset(&t, 0, sizeof t);
                 t.solve = solve_index;
@@ -380,7 +420,7 @@ int group_rebuild(Group& g, hipStream_t stream) {
     std::vector<Tile> tiles;
     for (size_t i = 0; i < g.members.size(); ++i) {
         descs.push_back(make_desc(*g.members[i]));
-        make_tiles(*g.members[i], (int)i, g.by, g.zc, tiles);
+        make_tiles(*g.members[i], (int)i, g.scheme, g.by, g.zc, (int)g.members.size(), tiles);
     }
     HIP_TRY(hipStreamSynchronize(stream));
     if ((int)descs.size() > g.desc_cap) {
@@ -413,11 +453,17 @@ int group_rebuild(Group& g, hipStream_t stream) {
     return HB_OK;
 }
 
-int kernels_per_step(const Group& g) { return g.stagewise ? 4 : 2; }
+int kernels_per_step(const Group& g) {
+    return g.scheme == SCHEME_STAGES ? 4 : g.scheme == SCHEME_PAIRS ? 2 : 1;
+}
 
-// kernel i of one step (stage i+1, or stage pair i)
+// kernel i of one step (the whole step, stage pair i, or stage i+1)
 int launch_step_kernel(const Group& g, int i, long long kstep, hipStream_t stream) {
-    if (g.stagewise)
+    if (g.scheme == SCHEME_STEP)
+        return from_hip(launch_step(g.prec, step_width(g.by), g.d_desc, g.d_tiles, g.ntiles, kstep,
+                                    stream),
+                        "step launch");
+    if (g.scheme == SCHEME_STAGES)
         return from_hip(launch_stage(g.prec, i + 1, g.by, g.d_desc, g.d_tiles, g.ntiles, kstep, stream),
                         "stage launch");
     return from_hip(launch_pair(g.prec, i, g.by, g.d_desc, g.d_tiles, g.ntiles, kstep, stream),
@@ -561,7 +607,8 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
     HB_TRY(solve_alloc(*h->s, *cfg, h->stream));
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
-    h->g.stagewise = (cfg->flags & HB_STAGEWISE) != 0;
+    h->g.scheme = scheme_of(cfg->flags);
+    h->g.by = h->g.scheme == SCHEME_STEP ? 8 : DEFAULT_BY;
     h->g.members.push_back(h->s.get());
     HIP_TRY(hipStreamSynchronize(h->stream));
     *out = h.release();
@@ -701,7 +748,7 @@ std::string tune_key(const Solve& s, int nmembers) {
     std::string name = "unknown";
     if (hipGetDeviceProperties(&p, dev) == hipSuccess) name = p.gcnArchName;
     std::ostringstream k;
-    k << name << "|prec" << s.cfg.precision << "|" << s.L.nx << "x" << s.L.ny << "x" << s.L.nz << "|m"
+    k << name << "|prec" << s.cfg.precision << "|scheme" << scheme_of(s.cfg.flags) << "|" << s.L.nx << "x" << s.L.ny << "x" << s.L.nz << "|m"
       << nmembers;
     return k.str();
 }
@@ -795,9 +842,15 @@ int group_autotune(Group& g, int trial_steps, hipStream_t stream, int* best_by, 
     std::vector<std::pair<int, int>> cand;
     int maxz = 0;
     for (Solve* s : g.members) maxz = std::max(maxz, s->L.nz);
-    for (int by : {8, 16})
-        for (int zc : {0, 16, 32, 64, 128})
-            if (zc <= maxz) cand.push_back({by, zc});
+    if (g.scheme == SCHEME_STEP) {
+        for (int by : {16, 8})
+            for (int zc : {0, 16, 32, 64, 128, 256})
+                if (zc <= maxz) cand.push_back({by, zc});
+    } else {
+        for (int by : {8, 16})
+            for (int zc : {0, 16, 32, 64, 128})
+                if (zc <= maxz) cand.push_back({by, zc});
+    }
     double best = 1e300;
     int bb = DEFAULT_BY, bz = 0;
     for (auto [by, zc] : cand) {
@@ -880,7 +933,11 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
         HB_TRY(solve_alloc(*s, cfgs[i], b->stream));
         HB_TRY(ensure_ctab(*s, 4096, b->stream, nullptr));
         b->groups[cfgs[i].precision].members.push_back(s.get());
-        if (cfgs[i].flags & HB_STAGEWISE) b->groups[cfgs[i].precision].stagewise = true;
+        if (i == 0)
+            for (Group& g : b->groups) {
+                g.scheme = scheme_of(cfgs[i].flags);
+                g.by = g.scheme == SCHEME_STEP ? 8 : DEFAULT_BY;
+            }
         b->use_graph = b->use_graph || (cfgs[i].flags & HB_USE_GRAPH);
         b->solves.push_back(std::move(s));
     }
@@ -996,6 +1053,7 @@ int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out
     }
     p->groups[0].prec = HB_F64;
     p->groups[1].prec = HB_F32C;
+    for (Group& g : p->groups) g.by = 8;  // whole-step scheme, 32-wide blocks
     *out = p.release();
     return HB_OK;
 }

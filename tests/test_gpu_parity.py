@@ -95,26 +95,32 @@ def test_graph_replay_bitwise(hb):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_stage_pair_scheme_equals_stagewise_bitwise(hb, precision):
-    w = si.small_case(75, 22, 19, seed=15, steps=11)
+@pytest.mark.parametrize("shape", [(75, 22, 19), (121, 25, 7), (3, 14, 30)])
+def test_schemes_bitwise_equal(hb, precision, shape):
+    """whole-step (default), stage-pair and per-stage kernels: same bits"""
+    w = si.small_case(*shape, seed=15, steps=11)
     a = run_gpu(hb, w, precision=precision)
-    b = run_gpu(hb, w, precision=precision, flags=hb.HB_STAGEWISE)
-    np.testing.assert_array_equal(a[0], b[0])
-    np.testing.assert_array_equal(a[1], b[1])
+    b = run_gpu(hb, w, precision=precision, flags=hb.HB_PAIRWISE)
+    c = run_gpu(hb, w, precision=precision, flags=hb.HB_STAGEWISE)
+    for x in (b, c):
+        np.testing.assert_array_equal(a[0], x[0])
+        np.testing.assert_array_equal(a[1], x[1])
 
 
-def test_stagewise_scheme_vs_oracle(hb, oracle_mod):
+@pytest.mark.parametrize("flags", ["HB_PAIRWISE", "HB_STAGEWISE"])
+def test_other_schemes_vs_oracle(hb, oracle_mod, flags):
     w = si.small_case(70, 21, 13, seed=16, steps=9)
-    g = run_gpu(hb, w, flags=hb.HB_STAGEWISE)
+    g = run_gpu(hb, w, flags=getattr(hb, flags))
     r = oracle.solve_workload(w)
     assert oracle.rel_maxnorm(*g, *r) <= TOL64
 
 
-def test_tiling_does_not_change_results(hb):
+@pytest.mark.parametrize("flags", [0, 8])
+def test_tiling_does_not_change_results(hb, flags):
     w = si.small_case(90, 30, 33, seed=9, steps=6)
-    ref = run_gpu(hb, w, tiling=(8, 0))
-    for t in [(16, 0), (8, 5), (16, 11), (8, 1)]:
-        got = run_gpu(hb, w, tiling=t)
+    ref = run_gpu(hb, w, tiling=(8, 0), flags=flags)
+    for t in [(16, 0), (8, 5), (16, 11), (8, 1), (16, 2)]:
+        got = run_gpu(hb, w, tiling=t, flags=flags)
         np.testing.assert_array_equal(ref[0], got[0])
         np.testing.assert_array_equal(ref[1], got[1])
 
