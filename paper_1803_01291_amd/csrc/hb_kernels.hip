@@ -541,29 +541,37 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const int zlast = z1 + 3;           // highest plane any stage-1+2 evaluation reads
 
     // rings indexed by (plane - zbase + 6) % 6 (+6: planes down to zbase-2)
-    T qp[6], qs[6];        // Y_phi, Y_psi of the own column
+    // Loads are issued at the end of a plane into the ring slot that plane
+    // has just freed: own Y two planes beyond the current window, outer-ring
+    // Y three planes ahead, so each load has about two planes of work to land.
+    T qp[6], qs[6];        // Y_phi, Y_psi of the own column (window zi-2..zi+2 + zi+3)
     T a3q[6], a4q[6];      // own-column S_phi,3 and S_phi,4
     T g1r[6], g2r[6];      // own-column G1, G2
-    T opr[2], osr[2];      // outer-ring Y, by plane parity
-    float lpr[2], lsr[2];  // FP32c low parts, by output-plane parity
+    T opr[3], osr[3];      // outer-ring Y, by plane mod 3
+    float lpr[3], lsr[3];  // FP32c low parts, by output plane mod 3
     for (int k = 0; k < 6; ++k) {
         qp[k] = qs[k] = a3q[k] = a4q[k] = g1r[k] = g2r[k] = T(0);
     }
-    opr[0] = opr[1] = osr[0] = osr[1] = T(0);
-    lpr[0] = lpr[1] = lsr[0] = lsr[1] = 0.f;
-    // prologue: own Y at planes zbase-2 .. zbase+2, outer ring at plane zbase
+    for (int k = 0; k < 3; ++k) {
+        opr[k] = osr[k] = T(0);
+        lpr[k] = lsr[k] = 0.f;
+    }
+    // prologue: own Y at planes zbase-2 .. zbase+3, outer ring at planes
+    // zbase .. zbase+2 (all <= z1+1 since a tile has >= 1 plane)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         const int p = zbase - 2 + k;
         const bool ok = col_ld && plane_ok(p);
         const long long o = (long long)p * sz + col_off;
         qp[(k + 4) % 6] = ldg(Yp, o, ok);
         qs[(k + 4) % 6] = ldg(Ys, o, ok);
     }
-    {
-        const bool ok = has_outer && outer_ld && plane_ok(zbase);
-        opr[0] = ldg(Yp, (long long)zbase * sz + outer_off, ok);
-        osr[0] = ldg(Ys, (long long)zbase * sz + outer_off, ok);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int p = zbase + k;
+        const bool ok = has_outer && outer_ld && plane_ok(p);
+        opr[k] = ldg(Yp, (long long)p * sz + outer_off, ok);
+        osr[k] = ldg(Ys, (long long)p * sz + outer_off, ok);
     }
 
     // one plane; PH = (zi - zbase) % 6 is a compile-time constant
@@ -572,42 +580,18 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         constexpr int B = PH & 1;                    // LDS double buffer
         constexpr int RS = PH % 3;                   // LDS ring slot of plane zi
         constexpr int RS2 = (PH + 1) % 3;            // ... of plane zi - 2
+        constexpr int OS = PH % 3;                   // outer / low-part slot of plane zi
+        constexpr int OS2 = (PH + 1) % 3;            // ... of plane zi - 2
         auto Q = [](int k) { return (PH + 6 + k) % 6; };  // ring slot of plane zi + k
         const int zi = zbase + it;
-
-        // prefetch: own Y at plane zi+3, outer ring at plane zi+1, FP32c low
-        // parts at the next output plane zi-1
-        {
-            const int p = zi + 3;
-            if (p <= zlast) {
-                const bool ok = col_ld && plane_ok(p);
-                const long long o = (long long)p * sz + col_off;
-                qp[Q(3)] = ldg(Yp, o, ok);
-                qs[Q(3)] = ldg(Ys, o, ok);
-            }
-            const int q = zi + 1;
-            if (q <= z1 + 1) {
-                const bool ok = has_outer && outer_ld && plane_ok(q);
-                opr[B ^ 1] = ldg(Yp, (long long)q * sz + outer_off, ok);
-                osr[B ^ 1] = ldg(Ys, (long long)q * sz + outer_off, ok);
-            }
-            if constexpr (COMP) {
-                const int zz = zi - 1;
-                if (zz >= z0 && zz < z1) {
-                    const long long o = (long long)zz * sz + col_off;
-                    lpr[B ^ 1] = ldg(d->lo_phi, o, own_st);
-                    lsr[B ^ 1] = ldg(d->lo_psi, o, own_st);
-                }
-            }
-        }
 
         // ---- stages 1 + 2 at plane zi over R2 ----
         const T yp0 = qp[Q(0)], ys0 = qs[Q(0)];
         pa[B][ry + 2][rx + 2] = yp0;
         pb[B][ry + 2][rx + 2] = yp0 + hdt * ys0;
         if (has_outer) {
-            pa[B][oy][ox] = opr[B];
-            pb[B][oy][ox] = opr[B] + hdt * osr[B];
+            pa[B][oy][ox] = opr[OS];
+            pb[B][oy][ox] = opr[OS] + hdt * osr[OS];
         }
         // the only barrier of the plane: it publishes this plane's stage-1+2
         // inputs and the ring slot written two planes ago (read below)
@@ -677,8 +661,8 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                 stg(Op, o, (T)(yp + dt6 * (ys + T(2) * k2 + T(2) * k3 + spsi4)));
                 stg(Os, o, (T)(ys + dt6 * (e1 + T(2) * e2 + T(2) * g3 + g4)));
             } else {
-                const double pp = (double)yp + (double)lpr[B];
-                const double ss = (double)ys + (double)lsr[B];
+                const double pp = (double)yp + (double)lpr[OS2];
+                const double ss = (double)ys + (double)lsr[OS2];
                 const double a1 = e1, a2 = e2, a3 = g3, a4 = g4;
                 const double k2 = ss + hdd * a1, k3 = ss + hdd * a2, k4 = ss + dtd * a3;
                 const double vp = pp + dt6 * (ss + 2.0 * k2 + 2.0 * k3 + k4);
@@ -688,6 +672,32 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                 stg((float*)Os, o, hs);
                 stg(d->lo_phi, o, (float)(vp - (double)hp));
                 stg(d->lo_psi, o, (float)(vs - (double)hs));
+            }
+        }
+
+        // ---- loads for later planes, into the slots this plane freed ----
+        {
+            const int p = zi + 4;  // slot of plane zi-2 (last used just above)
+            if (p <= zlast) {
+                const bool ok = col_ld && plane_ok(p);
+                const long long o = (long long)p * sz + col_off;
+                qp[Q(4)] = ldg(Yp, o, ok);
+                qs[Q(4)] = ldg(Ys, o, ok);
+            }
+            const int q = zi + 3;  // slot of plane zi (used before the barrier)
+            if (q <= z1 + 1) {
+                const bool ok = has_outer && outer_ld && plane_ok(q);
+                opr[OS] = ldg(Yp, (long long)q * sz + outer_off, ok);
+                osr[OS] = ldg(Ys, (long long)q * sz + outer_off, ok);
+            }
+            if constexpr (COMP) {
+                // low parts of output plane zi (updated two planes from now);
+                // the slot held output plane zi-3's, used one plane ago
+                if (zi >= z0 && zi < z1) {
+                    const long long o = (long long)zi * sz + col_off;
+                    lpr[OS] = ldg(d->lo_phi, o, own_st);
+                    lsr[OS] = ldg(d->lo_psi, o, own_st);
+                }
             }
         }
     };
