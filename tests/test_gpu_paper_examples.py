@@ -1,0 +1,97 @@
+"""The paper's section 3 examples on the GPU path at reduced resolution.
+
+Unit box [0,1]^3 (cell-centred), L = 5 (inv_L2 = 1/25), the paper's bump
+B(x; C, R) = exp(1/R^2 - 1/(R^2 - |x-C|^2)) with C the box centre.  Each run
+is checked against the oracle at the same resolution (same discrete
+problem) and against the facts the paper prints (tests/golden/
+paper_facts.json).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+FACTS = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+
+
+def unit_box_case(n, amp0, amp1, R, mu2, lam, dt):
+    nn, lo, hi = (n, n, n), (0.0,) * 3, (1.0,) * 3
+    b = si.paper_bump(nn, lo, hi, (0.5, 0.5, 0.5), R)
+    w = si.Workload(f"paper_unit{n}", nn, lo, hi, mu2=mu2, lam=lam, dt=dt, steps=0,
+                    inv_L2=1.0 / 25.0, phi0=lambda: amp0 * b, phi1=lambda: amp1 * b)
+    return w
+
+
+def run_segments(hb, w, segments):
+    """Advance through the given step counts; return the states after each."""
+    p0, p1 = w.initial()
+    h = hb.hb_create(hb.config_from_workload(w))
+    out = []
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        for k in segments:
+            hb.hb_step(h, k)
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_read(h, phi, psi)
+            out.append((phi, psi, hb.hb_diagnostics(h)))
+    finally:
+        hb.hb_destroy(h)
+    return out
+
+
+def test_example3_bubble_onset(hb, oracle_mod):
+    f = FACTS["example3_bubble_onset"]
+    dt = 1e-3
+    w = unit_box_case(96, 1.0, f["phi1_factor"], f["bump_radius"], f["mu2"], f["lambda"], dt)
+    n1 = int(round(f["positive_at"] / dt))
+    n2 = int(round(f["sign_change_at"] / dt)) - n1
+    (a, sa, da), (b, sb, db) = run_segments(hb, w, [n1, n2])
+    # same discrete problem on the oracle
+    r = oracle.solve_workload(w, nsteps=n1 + n2)
+    assert oracle.rel_maxnorm(b, sb, *r) <= 1e-12
+    scale = np.max(np.abs(b))
+    print(f"Example 3 (96^3): min phi {a.min():.3e} at t={f['positive_at']}, "
+          f"{b.min():.3e} at t={f['sign_change_at']} (max {scale:.3e})")
+    assert a.min() > -1e-4 * scale          # still positive (up to the stencil's far-field dust)
+    assert b.min() < -0.1 * scale           # sign change: a bubble wall has formed
+    assert db["negative"] > 0
+
+
+def test_example5_no_bubble(hb):
+    f = FACTS["example5_no_bubble"]
+    dt = 2e-3
+    w = unit_box_case(64, f["amp"], 0.0, f["bump_radius"], f["mu2"], f["lambda"], dt)
+    segs = [50] * int(round(f["until"] / dt / 50))
+    worst = 0.0
+    for phi, psi, d in run_segments(hb, w, segs):
+        worst = min(worst, phi.min() / np.max(np.abs(phi)))
+    print(f"Example 5 (64^3): most negative phi / max phi over t <= {f['until']}: {worst:.3e}")
+    assert worst > -1e-4
+
+
+def test_example4_plateau_and_P(hb):
+    f = FACTS["example4_long_time_plateau"]
+    dt = 2e-3
+    n = 64
+    w = unit_box_case(n, 1.0, f["phi1_factor"], f["bump_radius"], f["mu2"], f["lambda"], dt)
+    k = int(round(1.0 / dt))
+    states = run_segments(hb, w, [k] * int(round(f["t"])))
+    phi, psi, d = states[-1]
+    c = n // 2
+    centre = phi[c - 1:c + 1, c - 1:c + 1, c - 1:c + 1].mean()  # the 8 nodes around the centre
+    P = [s[2]["lap_max"] for s in states]
+    print(f"Example 4 (64^3): bubble-centre phi at t={f['t']}: {centre:.5f}; "
+          f"P(t) at t=1..{int(f['t'])}: " + " ".join(f"{p:.2e}" for p in P))
+    assert round(centre, f["decimals"]) == f["value"]
+    assert abs(centre + math.sqrt(f["mu2"] / f["lambda"])) < 5e-3
+    # P(t) = c(t) max|Lap_h phi| goes to zero; once the step function has
+    # formed, max|Lap_h phi| settles and P falls like c(t) ~ e^{-2t}
+    ratios = [P[i + 1] / P[i] for i in range(4, len(P) - 1)]
+    assert all(r < 0.2 for r in ratios), ratios
+    assert P[-1] < 1e-5 * P[0]
