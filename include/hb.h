@@ -212,6 +212,33 @@ int hb_pool_read(hb_pool* p, int slot, void* phi, void* phi_t, int mem, int dtyp
 int hb_pool_release(hb_pool* p, int slot);
 int hb_pool_destroy(hb_pool* p);
 
+/* ---- batched radial solves (section 2.2, eq. (radial)) ---------------------- */
+
+/* One radial solve: nodes r_i = i dr, i = 0..m-1, with phi = 0 at r = m dr
+ * (the outer zero boundary), phi_r(0) = 0 through the symmetric ghost of
+ * section 2.2, the operator 2/r phi_r + phi_rr with the fourth-order central
+ * first and second differences (3 phi_rr at r = 0 by L'Hospital's rule), and
+ * classical RK4 from t0 for `steps` steps of dt. */
+typedef struct hb_radial_config {
+    int32_t m;        /* 1 <= m <= HB_RADIAL_MAX_NODES                      */
+    uint32_t flags;   /* HB_ALLOW_UNSTABLE                                  */
+    double dr;        /* node spacing (> 0)                                 */
+    double mu2, lambda, inv_L2, t0, dt;
+    int64_t steps;    /* >= 0                                               */
+} hb_radial_config;
+
+#define HB_RADIAL_MAX_NODES 2700
+
+/* Advance `count` independent radial solves in one launch (one workgroup per
+ * solve; every solve runs all its steps inside the kernel).  phi and psi hold
+ * the solves' nodes back to back (solve k starts after the m of solves
+ * 0..k-1), FP64, in `mem` (HB_HOST or HB_DEVICE); they are read as the
+ * initial state and overwritten with the final state.  Waits for completion.
+ * Stability: dt sqrt(c0 16/dr^2) <= 2 sqrt(2), c0 = inv_L2 exp(-2 t0),
+ * else HB_E_CFL (unless HB_ALLOW_UNSTABLE).  stream: hipStream_t or NULL. */
+int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi, int mem,
+                    void* stream);
+
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Streamed-bandwidth probe on the current device (the achievable HBM ceiling

@@ -82,4 +82,17 @@ int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, do
 int launch_probe(int kind, void* const* in, void* const* out, long long n16, int blocks,
                  void* stream);
 
+// Batched radial solves (section 2.2 form): one workgroup per solve, state in
+// LDS, all steps in one launch.  phi/psi hold the solves back to back.
+struct RadialDesc {
+    long long offset;  // first node of this solve in phi/psi
+    long long steps;
+    int m;             // nodes r_i = i dr, i = 0..m-1 (phi = 0 at r = m dr)
+    int pad_;
+    double dr, mu2, lambda, inv_L2, t0, dt;
+};
+size_t radial_lds_bytes(int max_m);
+int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
+                  void* stream);
+
 }  // namespace hb

@@ -1223,3 +1223,80 @@ extern "C" int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, d
         if (p) (void)hipFree(p);
     return rc;
 }
+
+// ---- batched radial solves ------------------------------------------------------
+
+extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi,
+                               int mem, void* stream) {
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!cfgs || !phi || !psi)))
+        return fail(HB_E_ARG, "bad radial batch arguments");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    if (count == 0) return HB_OK;
+    std::vector<RadialDesc> descs(count);
+    long long total = 0;
+    int max_m = 0;
+    for (int i = 0; i < count; ++i) {
+        const hb_radial_config& c = cfgs[i];
+        if (c.m < 1 || c.m > HB_RADIAL_MAX_NODES)
+            return fail(HB_E_ARG, "radial solve %d: m = %d outside [1, %d]", i, c.m, HB_RADIAL_MAX_NODES);
+        if (!(c.dr > 0) || !(c.dt > 0) || !std::isfinite(c.dr) || !std::isfinite(c.dt) || c.steps < 0)
+            return fail(HB_E_ARG, "radial solve %d: need dr > 0, dt > 0, steps >= 0", i);
+        if (!std::isfinite(c.mu2) || !std::isfinite(c.lambda) || !std::isfinite(c.inv_L2) ||
+            !std::isfinite(c.t0) || c.inv_L2 < 0)
+            return fail(HB_E_ARG, "radial solve %d: coefficients must be finite (inv_L2 >= 0)", i);
+        if (!(c.flags & HB_ALLOW_UNSTABLE)) {
+            const double c0 = c.inv_L2 * std::exp(-2.0 * c.t0);
+            if (c.dt * std::sqrt(c0 * 16.0 / (c.dr * c.dr)) > 2.0 * std::sqrt(2.0))
+                return fail(HB_E_CFL, "radial solve %d: dt = %g beyond the stability limit", i, c.dt);
+        }
+        RadialDesc& d = descs[i];
+        std::memset(&d, 0, sizeof d);
+        d.offset = total;
+        d.steps = c.steps;
+        d.m = c.m;
+        d.dr = c.dr;
+        d.mu2 = c.mu2;
+        d.lambda = c.lambda;
+        d.inv_L2 = c.inv_L2;
+        d.t0 = c.t0;
+        d.dt = c.dt;
+        total += c.m;
+        max_m = std::max(max_m, c.m);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)total * sizeof(double);
+    RadialDesc* d_desc = nullptr;
+    double* dphi = nullptr;
+    double* dpsi = nullptr;
+    int rc = HB_OK;
+    if (hipMalloc((void**)&d_desc, descs.size() * sizeof(RadialDesc)) != hipSuccess)
+        rc = fail(HB_E_NOMEM, "radial descriptor allocation");
+    if (rc == HB_OK && mem == HB_HOST) {
+        if (hipMalloc((void**)&dphi, bytes) != hipSuccess || hipMalloc((void**)&dpsi, bytes) != hipSuccess)
+            rc = fail(HB_E_NOMEM, "radial state allocation");
+    } else {
+        dphi = phi;
+        dpsi = psi;
+    }
+    if (rc == HB_OK)
+        rc = from_hip(hipMemcpyAsync(d_desc, descs.data(), descs.size() * sizeof(RadialDesc),
+                                     hipMemcpyHostToDevice, s), "radial descriptors");
+    if (rc == HB_OK && mem == HB_HOST) {
+        rc = from_hip(hipMemcpyAsync(dphi, phi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
+        if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(dpsi, psi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
+    }
+    if (rc == HB_OK) rc = from_hip(launch_radial(d_desc, count, max_m, dphi, dpsi, s), "radial launch");
+    if (rc == HB_OK && mem == HB_HOST) {
+        rc = from_hip(hipMemcpyAsync(phi, dphi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");
+        if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(psi, dpsi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc == HB_OK && e != hipSuccess) rc = fail(HB_E_HIP, "radial sync: %s", hipGetErrorString(e));
+    if (d_desc) (void)hipFree(d_desc);
+    if (mem == HB_HOST) {
+        if (dphi) (void)hipFree(dphi);
+        if (dpsi) (void)hipFree(dpsi);
+    }
+    return rc;
+}

@@ -43,6 +43,15 @@ class hb_config(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("stream", ctypes.c_void_p)]
 
 
+class hb_radial_config(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("flags", ctypes.c_uint32), ("dr", ctypes.c_double),
+                ("mu2", ctypes.c_double), ("lambda_", ctypes.c_double), ("inv_L2", ctypes.c_double),
+                ("t0", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+HB_RADIAL_MAX_NODES = 2700
+
+
 class hb_diag(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("step", ctypes.c_int64), ("integral", ctypes.c_double),
                 ("l2_phi", ctypes.c_double), ("l2_psi", ctypes.c_double),
@@ -90,6 +99,7 @@ _SIGS = {
     "hb_pool_release": [_P, _I],
     "hb_pool_destroy": [_P],
     "hb_probe_bandwidth": [_I, ctypes.c_size_t, _I, ctypes.POINTER(ctypes.c_double)],
+    "hb_radial_solve": [_I, ctypes.POINTER(hb_radial_config), _P, _P, _I, _P],
 }
 
 
@@ -372,3 +382,24 @@ def hb_probe_bandwidth(kind: int, bytes_per_array: int, iters: int = 20) -> floa
     g = ctypes.c_double()
     _check(load().hb_probe_bandwidth(int(kind), int(bytes_per_array), int(iters), ctypes.byref(g)))
     return g.value
+
+
+# ---- batched radial solves ------------------------------------------------------------
+
+def make_radial_config(m: int, dr: float, mu2: float, lam: float, dt: float, steps: int,
+                       t0: float = 0.0, inv_L2: float = 1.0, flags: int = 0) -> hb_radial_config:
+    c = hb_radial_config()
+    c.m, c.flags, c.dr, c.mu2, c.lambda_ = int(m), int(flags), float(dr), float(mu2), float(lam)
+    c.inv_L2, c.t0, c.dt, c.steps = float(inv_L2), float(t0), float(dt), int(steps)
+    return c
+
+
+def hb_radial_solve(cfgs, phi, psi, stream=None) -> None:
+    """Advance the solves in place; phi/psi: FP64 NumPy arrays (host) or torch
+    tensors (device) holding the solves back to back."""
+    arr = (hb_radial_config * len(cfgs))(*cfgs)
+    p0, m0, d0, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(psi)
+    if d0 != HB_DTYPE_F64 or d1 != HB_DTYPE_F64 or m0 != m1:
+        raise TypeError("phi and psi must be FP64 and in the same memory")
+    _check(load().hb_radial_solve(len(cfgs), arr, p0, p1, m0, stream))
