@@ -67,6 +67,39 @@ __device__ __forceinline__ void stg(T* p, long long off, T v) {
     ((gptr<T>)p)[off] = v;
 }
 
+// Raw buffer access to one x-y plane of a field.  The resource's base is the
+// plane's cell (-2, -2) and its size the plane's bytes.  Loads and stores go
+// through buffer instructions with a per-lane 32-bit byte offset: a store
+// whose offset lies past the plane is dropped by the hardware range check,
+// which is how lanes without an output column skip a store without a branch.
+// (Branch-free memory code keeps the number of memory operations between a
+// load and its use the same on every path, so the wait before the use can
+// leave the later prefetches in flight.)
+constexpr int BUF_DWORD3 = 0x00020000;   // raw untyped buffer, gfx9 family
+constexpr uint32_t BUF_SKIP = 0x80000000u;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(unsigned long long base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, BUF_DWORD3);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
+}
+
 template <typename T, int STAGE, bool COMP>
 struct OwnRec {
     T p, s, g1, g2, g3;
@@ -505,18 +538,39 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const int tid = threadIdx.x;
     const int rx = tid % SK_RX, ry = tid / SK_RX;
     const int gx = tl.x0 - 2 + rx, gy = tl.y0 - 2 + ry;
-    const bool col_ld = (gx >= -2) && (gx < nx + 2) && (gy >= -2) && (gy < ny + 2);
     const bool col_int = (gx >= 0) && (gx < nx) && (gy >= 0) && (gy < ny);
     const bool core = (rx >= 2) && (rx < SK_RX - 2) && (ry >= 2) && (ry < SK_RY - 2);
     const bool own_st = core && col_int;
-    const long long col_off = (long long)gy * sy + gx;
+
+    // Loads are not predicated: a column or plane outside the stored range
+    // [-2, n + 2) is clamped onto the nearest halo cell, which holds zero for
+    // the life of the solve, so the loaded value is the zero the stencil
+    // needs there.  A plane is addressed through a buffer resource (scalar
+    // registers) and a thread's column by a 32-bit byte offset within the
+    // plane, measured from the plane's cell (-2, -2); a plane is under 2 GiB.
+    auto col_bytes = [&](int x, int y) -> uint32_t {
+        const int cx = min(max(x, -2), nx + 1), cy = min(max(y, -2), ny + 1);
+        return (uint32_t)(((long long)(cy + 2) * sy + (cx + 2)) * (long long)sizeof(T));
+    };
+    const uint32_t col_b = col_bytes(gx, gy);
+    // plane p of a field starts (at its cell (-2, -2)) p * pbytes bytes past
+    // the field's corner address; the products are 32 x 32 -> 64-bit scalar
+    // multiplies and the bases scalar adds
+    const int pbytes = (int)(sz * (long long)sizeof(T));
+    const long long cb = (2 * sy + 2) * (long long)sizeof(T);
+    const unsigned long long bYp = (unsigned long long)Yp - cb, bYs = (unsigned long long)Ys - cb;
+    const unsigned long long bOp = (unsigned long long)Op - cb, bOs = (unsigned long long)Os - cb;
+    const unsigned long long bLp = (unsigned long long)d->lo_phi - cb;
+    const unsigned long long bLs = (unsigned long long)d->lo_psi - cb;
+    auto poff = [&](int p) -> unsigned long long { return (unsigned long long)((long long)p * pbytes); };
+    auto rs = [&](unsigned long long b, unsigned long long off) { return plane_rsrc(b + off, pbytes); };
+    auto clampz = [&](int p) { return min(max(p, -2), nz + 1); };
 
     // outer ring (R4 minus R2): rows 0,1 and QY-2,QY-1 of R4, then columns
     // 0,1 and QX-2,QX-1 of the middle rows
-    bool has_outer = false, outer_ld = false;
+    const bool has_outer = tid < SK_NOUTER;
     int ox = 0, oy = 0;
-    long long outer_off = 0;
-    if (tid < SK_NOUTER) {
+    if (has_outer) {
         if (tid < 4 * SK_QX) {
             const int r = tid / SK_QX;
             oy = (r < 2) ? r : SK_QY - 4 + r;
@@ -527,18 +581,17 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             oy = 2 + (h >> 2);
             ox = (k < 2) ? k : SK_QX - 4 + k;
         }
-        has_outer = true;
-        const int hx = tl.x0 - 4 + ox, hy = tl.y0 - 4 + oy;
-        outer_ld = (hx >= -2) && (hx < nx + 2) && (hy >= -2) && (hy < ny + 2);
-        outer_off = (long long)hy * sy + hx;
     }
-
-    auto plane_ok = [&](int p) { return p >= -2 && p < nz + 2; };
+    // threads without an outer-ring column load the plane's corner cell (a
+    // halo zero), so every thread issues the same loads
+    const uint32_t outer_b = has_outer ? col_bytes(tl.x0 - 4 + ox, tl.y0 - 4 + oy) : 0u;
+    const uint32_t lo_b = own_st ? col_b : 0u;           // FP32c low parts
+    const uint32_t out_b = own_st ? col_b : BUF_SKIP;    // output column or none
 
     const int z0 = tl.z0, z1 = tl.z1;
     const int zbase = z0 - 2;           // first plane of stages 1+2
-    const int niter = z1 - z0 + 4;      // planes zbase .. z1+1
-    const int zlast = z1 + 3;           // highest plane any stage-1+2 evaluation reads
+    const int niter = z1 - z0 + 4;      // planes zbase .. z1+1 carry work
+    const int zlast = min(z1 + 3, nz + 1);  // highest plane a needed evaluation reads
 
     // rings indexed by (plane - zbase + 6) % 6 (+6: planes down to zbase-2)
     // Loads are issued at the end of a plane into the ring slot that plane
@@ -557,22 +610,34 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         lpr[k] = lsr[k] = 0.f;
     }
     // prologue: own Y at planes zbase-2 .. zbase+3, outer ring at planes
-    // zbase .. zbase+2 (all <= z1+1 since a tile has >= 1 plane)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    // zbase .. zbase+2, issued in the order the march issues them (own plane
+    // p, then outer plane p-1), so the waits in the march's first pass are
+    // those of every later pass
+    auto ld_own = [&](int k) {
         const int p = zbase - 2 + k;
-        const bool ok = col_ld && plane_ok(p);
-        const long long o = (long long)p * sz + col_off;
-        qp[(k + 4) % 6] = ldg(Yp, o, ok);
-        qs[(k + 4) % 6] = ldg(Ys, o, ok);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
+        const unsigned long long o = poff(clampz(p));
+        qp[(k + 4) % 6] = bload<T>(rs(bYp, o), col_b);
+        qs[(k + 4) % 6] = bload<T>(rs(bYs, o), col_b);
+    };
+    auto ld_outer = [&](int k) {
         const int p = zbase + k;
-        const bool ok = has_outer && outer_ld && plane_ok(p);
-        opr[k] = ldg(Yp, (long long)p * sz + outer_off, ok);
-        osr[k] = ldg(Ys, (long long)p * sz + outer_off, ok);
-    }
+        const unsigned long long o = poff(clampz(p));
+        opr[k] = bload<T>(rs(bYp, o), outer_b);
+        osr[k] = bload<T>(rs(bYs, o), outer_b);
+    };
+    ld_own(0);
+    ld_own(1);
+    ld_own(2);
+    ld_own(3);
+    ld_outer(0);
+    ld_own(4);
+    ld_outer(1);
+    ld_own(5);
+    ld_outer(2);
+    // The first plane needs almost all of these.  Waiting for all of them
+    // here also leaves no prologue load pending at the head of the march,
+    // so the waits inside it are set by the march's own steady pattern.
+    __builtin_amdgcn_s_waitcnt(0);
 
     // one plane; PH = (zi - zbase) % 6 is a compile-time constant
     auto plane = [&](auto ph, int it) {
@@ -633,7 +698,10 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 
         // ---- stages 3 + 4 and the update at plane z = zi - 2 on the tile ----
         const int z = zi - 2;
-        if (z >= z0 && own_st) {
+        const bool zout = z >= z0 && z < z1;
+        T op_ = T(0), os_ = T(0);
+        float ol_p = 0.f, ol_s = 0.f;
+        if (zout && own_st) {
             const T SA = a3q[Q(-2)], SB = a4q[Q(-2)];
             T lapA = w0 * SA;
             lapA += w1x * (r3[RS2][ry][rx - 1] + r3[RS2][ry][rx + 1]);
@@ -654,12 +722,11 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             const T g3 = -T(3) * spsi3 + c3 * lapA + mu2 * SA - lam * SA * SA * SA;
             const T spsi4 = ys + dtT * g3;
             const T g4 = -T(3) * spsi4 + c4 * lapB + mu2 * SB - lam * SB * SB * SB;
-            const long long o = (long long)z * sz + col_off;
             if constexpr (!COMP) {
                 const T k2 = ys + hdt * e1;
                 const T k3 = ys + hdt * e2;
-                stg(Op, o, (T)(yp + dt6 * (ys + T(2) * k2 + T(2) * k3 + spsi4)));
-                stg(Os, o, (T)(ys + dt6 * (e1 + T(2) * e2 + T(2) * g3 + g4)));
+                op_ = (T)(yp + dt6 * (ys + T(2) * k2 + T(2) * k3 + spsi4));
+                os_ = (T)(ys + dt6 * (e1 + T(2) * e2 + T(2) * g3 + g4));
             } else {
                 const double pp = (double)yp + (double)lpr[OS2];
                 const double ss = (double)ys + (double)lsr[OS2];
@@ -668,37 +735,45 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                 const double vp = pp + dt6 * (ss + 2.0 * k2 + 2.0 * k3 + k4);
                 const double vs = ss + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
                 const float hp = (float)vp, hs = (float)vs;
-                stg((float*)Op, o, hp);
-                stg((float*)Os, o, hs);
-                stg(d->lo_phi, o, (float)(vp - (double)hp));
-                stg(d->lo_psi, o, (float)(vs - (double)hs));
+                op_ = hp;
+                os_ = hs;
+                ol_p = (float)(vp - (double)hp);
+                ol_s = (float)(vs - (double)hs);
+            }
+        }
+        // stores outside the branch: lanes and planes without output use an
+        // offset past the plane, which the buffer range check drops
+        {
+            // (outside [z0, z1) no lane stores, so the base of plane z is
+            // never dereferenced even where z is outside the field)
+            const uint32_t ob = zout ? out_b : BUF_SKIP;
+            const unsigned long long o = poff(z);
+            bstore<T>(rs(bOp, o), ob, op_);
+            bstore<T>(rs(bOs, o), ob, os_);
+            if constexpr (COMP) {
+                bstore<float>(rs(bLp, o), ob, ol_p);
+                bstore<float>(rs(bLs, o), ob, ol_s);
             }
         }
 
         // ---- loads for later planes, into the slots this plane freed ----
-        {
-            const int p = zi + 4;  // slot of plane zi-2 (last used just above)
-            if (p <= zlast) {
-                const bool ok = col_ld && plane_ok(p);
-                const long long o = (long long)p * sz + col_off;
-                qp[Q(4)] = ldg(Yp, o, ok);
-                qs[Q(4)] = ldg(Ys, o, ok);
-            }
-            const int q = zi + 3;  // slot of plane zi (used before the barrier)
-            if (q <= z1 + 1) {
-                const bool ok = has_outer && outer_ld && plane_ok(q);
-                opr[OS] = ldg(Yp, (long long)q * sz + outer_off, ok);
-                osr[OS] = ldg(Ys, (long long)q * sz + outer_off, ok);
-            }
-            if constexpr (COMP) {
-                // low parts of output plane zi (updated two planes from now);
-                // the slot held output plane zi-3's, used one plane ago
-                if (zi >= z0 && zi < z1) {
-                    const long long o = (long long)zi * sz + col_off;
-                    lpr[OS] = ldg(d->lo_phi, o, own_st);
-                    lsr[OS] = ldg(d->lo_psi, o, own_st);
-                }
-            }
+        // (unconditional: past the planes a tile reads, the plane index is
+        // clamped and the value is never used)
+        // own plane zi+4 into the slot of plane zi-2 (last used just above);
+        // zi+4 >= z0+2 >= 2, and planes past nz+1 are never needed
+        const unsigned long long op4 = poff(min(zi + 4, zlast));
+        qp[Q(4)] = bload<T>(rs(bYp, op4), col_b);
+        qs[Q(4)] = bload<T>(rs(bYs, op4), col_b);
+        // outer plane zi+3 into the slot of plane zi (used before the barrier)
+        const unsigned long long oq3 = poff(min(zi + 3, z1 + 1));
+        opr[OS] = bload<T>(rs(bYp, oq3), outer_b);
+        osr[OS] = bload<T>(rs(bYs, oq3), outer_b);
+        if constexpr (COMP) {
+            // low parts of output plane zi (updated two planes from now);
+            // the slot held output plane zi-3's, used one plane ago
+            const unsigned long long ol = poff(min(zi, z1));
+            lpr[OS] = bload<float>(rs(bLp, ol), lo_b);
+            lsr[OS] = bload<float>(rs(bLs, ol), lo_b);
         }
     };
 
@@ -708,15 +783,18 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     using I3 = std::integral_constant<int, 3>;
     using I4 = std::integral_constant<int, 4>;
     using I5 = std::integral_constant<int, 5>;
-    // niter = z1 - z0 + 4 >= 5 planes; the block-uniform guards keep every
-    // thread on the same sequence of barriers
-    for (int it = 0; it < niter; it += 6) {
+    // The march runs a multiple of 6 planes so that every pass of the loop
+    // body is the same straight-line code (no per-plane exits); planes past
+    // z1+1 compute values nothing reads and store nothing.  Every thread runs
+    // the same sequence of barriers.
+    const int nplanes = (niter + 5) / 6 * 6;
+    for (int it = 0; it < nplanes; it += 6) {
         plane(I0{}, it);
-        if (it + 1 < niter) plane(I1{}, it + 1);
-        if (it + 2 < niter) plane(I2{}, it + 2);
-        if (it + 3 < niter) plane(I3{}, it + 3);
-        if (it + 4 < niter) plane(I4{}, it + 4);
-        if (it + 5 < niter) plane(I5{}, it + 5);
+        plane(I1{}, it + 1);
+        plane(I2{}, it + 2);
+        plane(I3{}, it + 3);
+        plane(I4{}, it + 4);
+        plane(I5{}, it + 5);
     }
 }
 

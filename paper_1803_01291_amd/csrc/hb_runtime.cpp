@@ -99,6 +99,13 @@ int validate(const hb_config* c) {
     if (!(c->dt > 0) || !std::isfinite(c->dt)) return fail(HB_E_ARG, "dt must be > 0");
     if (c->inv_L2 < 0) return fail(HB_E_ARG, "inv_L2 must be >= 0");
     if (c->precision != HB_F64 && c->precision != HB_F32C) return fail(HB_E_ARG, "bad precision");
+    {
+        // the whole-step kernel addresses a plane with 32-bit byte offsets
+        const Layout L = plan_layout(*c);
+        if ((double)L.sz * L.esz >= 2147483648.0)
+            return fail(HB_E_ARG, "an x-y plane (%lld x %lld padded cells) must be under 2 GiB",
+                        L.sy, (long long)c->n[1] + 4);
+    }
     if (!(c->flags & HB_ALLOW_UNSTABLE)) {
         // RK4 is stable on the imaginary axis up to |z| = 2 sqrt(2); -Lap_h has
         // spectral radius sum_d 16/(3 h_d^2) (symbol (1-cos)(7-cos)/3 <= 16/3)

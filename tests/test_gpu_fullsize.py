@@ -8,6 +8,8 @@ default tiling, stage-pair kernels).
 * 256^3 x 10 steps: every node against the oracle run here.
 * 512^3 x 1000 steps: FP64 vs the stored oracle samples; FP32c against FP64
   (max and L2 error over the whole grid, and at the samples vs the oracle).
+* 64 uneven solves x 500 steps in one batched launch (graph replay, as timed):
+  solves 0, 1, 2 vs the stored oracle samples; FP32c batch vs FP64 batch.
 """
 import json
 import os
@@ -92,3 +94,32 @@ def test_cube512_fp64_and_fp32c(hb):
           f"{e32:.3e}; FP32c vs FP64 whole grid: max {dmax:.3e}, relative L2 {l2 / l2ref:.3e}")
     assert e64 <= 1e-12
     assert e32 <= 1e-5 and dmax <= 1e-5 and l2 / l2ref <= 1e-5
+
+
+def test_batch64_500_steps_vs_oracle_samples(hb):
+    g = load_gold("batch64_oracle.json")
+    ws = si.batch_config()
+    steps = ws[0].steps
+    outs = {}
+    for prec in (0, 1):
+        cfgs = [hb.config_from_workload(w, prec, hb.HB_USE_GRAPH) for w in ws]
+        b = hb.hb_batch_create(cfgs)
+        try:
+            for i, w in enumerate(ws):
+                hb.hb_batch_set_initial(b, i, w.initial()[0], None)
+            hb.hb_batch_step(b, steps)
+            for i in g["solves"]:
+                p0 = np.empty(ws[i].n[::-1], np.float64)
+                phi, psi = np.empty_like(p0), np.empty_like(p0)
+                hb.hb_batch_read(b, i, phi, psi)
+                outs[(prec, i)] = (phi, psi)
+        finally:
+            hb.hb_batch_destroy(b)
+    for i, rec in zip(g["solves"], g["records"]):
+        assert ws[i].name == rec["workload"] and rec["steps"] == steps
+        e64 = sampled_error(rec, *outs[(0, i)])
+        e32 = sampled_error(rec, *outs[(1, i)])
+        print(f"batch solve {i} ({rec['workload']}): FP64 sampled error {e64:.3e}, "
+              f"FP32c {e32:.3e}")
+        assert e64 <= 1e-12
+        assert e32 <= 1e-5
