@@ -150,11 +150,13 @@ int hb_sync(hb_solver* s);
  * HB_E_NONFINITE (with *out filled) when the state holds NaN/Inf. */
 int hb_diagnostics(hb_solver* s, hb_diag* out);
 
-/* Tile shape: zc >= 1 planes per tile (0 = library default); by in {8, 16}:
- * rows of 64 columns per tile for the stage-pair and per-stage kernels
- * (default 16); for the whole-step kernel by = 8 selects 28 x 12 tiles
- * (512-thread blocks, two per CU; the default) and by = 16 selects 60 x 12
- * tiles (1024-thread blocks).  Results do not depend on it. */
+/* Tile shape: zc >= 1 planes per tile (0 = library default: for the
+ * whole-step kernel, the length that best fills whole rounds of resident
+ * blocks on the device); by in {8, 16}: rows of 64 columns per tile for the
+ * stage-pair and per-stage kernels (default 16); for the whole-step kernel
+ * by = 8 selects 32 x 24 tiles (1008-thread blocks; the FP64 default) and
+ * by = 16 selects 60 x 12 tiles (1024-thread blocks; the FP32c default).
+ * Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 
 /* Time every candidate tile shape for `trial_steps` steps on the current

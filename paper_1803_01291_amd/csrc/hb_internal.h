@@ -51,11 +51,17 @@ int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile
 // (writes the next state).  Bitwise equal to the four per-stage launches.
 int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream);
-// Whole-step kernel: one launch per RK4 step.  `width` (64 or 32) is the
-// x-extent of the region a block's threads own; its tiles are (width - 4) x
-// STEP_TILE_Y interior columns.  Bitwise equal to the stage-pair kernels.
-constexpr int STEP_TILE_Y = 12;
-int launch_step(int prec, int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
+// Whole-step kernel: one launch per RK4 step.  A block's threads own an
+// rx x ry region: its interior tile of (rx - 4) x (ry - 4) columns plus a
+// 2-cell ring.  Shapes (`shape` indexes this table), both 16 waves per CU:
+// 36 x 28 (1008 threads; tiles 32 columns wide, so x-tiles start on 128-byte
+// lines and cover power-of-two widths exactly) and 64 x 16 (1024 threads).
+// Bitwise equal to the stage-pair kernels.
+struct StepShape {
+    int rx, ry, blocks_per_cu;
+};
+constexpr StepShape STEP_SHAPES[2] = {{36, 28, 1}, {64, 16, 1}};
+int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream);
 int launch_tick(SolveDesc* descs, int count, long long k, void* stream);
 int launch_set_target(SolveDesc* descs, int index, long long target, void* stream);

@@ -100,6 +100,94 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, T
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
 }
 
+// ---- per-point arithmetic shared by every kernel ----
+// Written as explicit operations (fused multiply-adds where named), with
+// contraction off, in one fixed order, so the per-stage, stage-pair and
+// whole-step kernels give bitwise-identical results.  The order keeps the
+// dependency chains short: the 13-point sum is built from axis partial sums,
+// and in the psi forcing the stencil term is added last, to a part formed
+// independently of the stencil.
+__device__ __forceinline__ double fm(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fm(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename T>
+struct PointCoef {
+    T w0, w1x, w1y, w1z, w2x, w2y, w2z, mu2, lam;
+    T hdt, dt, m3h, m3d;  // dt/2, dt, -3 dt/2, -3 dt
+};
+
+template <typename T>
+__device__ __forceinline__ PointCoef<T> point_coef(const SolveDesc* d) {
+    PointCoef<T> k;
+    k.w0 = (T)d->w0;
+    k.w1x = (T)d->w1[0]; k.w1y = (T)d->w1[1]; k.w1z = (T)d->w1[2];
+    k.w2x = (T)d->w2[0]; k.w2y = (T)d->w2[1]; k.w2z = (T)d->w2[2];
+    k.mu2 = (T)d->mu2;
+    k.lam = (T)d->lambda;
+    k.hdt = (T)d->hdt;
+    k.dt = (T)d->dt;
+    k.m3h = T(-3) * k.hdt;
+    k.m3d = T(-3) * k.dt;
+    return k;
+}
+
+// x-y part of Lap_h at a point (eq. (lap)): centre value c and the neighbour
+// pair sums x1 = S(x-1) + S(x+1), x2 = S(x-2) + S(x+2), y1, y2 likewise
+template <typename T>
+__device__ __forceinline__ T lap_xy(const PointCoef<T>& k, T c, T x1, T x2, T y1, T y2) {
+#pragma clang fp contract(off)
+    const T ax = fm(k.w2x, x2, k.w1x * x1);
+    const T ay = fm(k.w2y, y2, k.w1y * y1);
+    return fm(k.w0, c, ax) + ay;
+}
+
+// Lap_h = x-y part + z part, z1 = S(z-1) + S(z+1), z2 = S(z-2) + S(z+2)
+template <typename T>
+__device__ __forceinline__ T lap_z(const PointCoef<T>& k, T xy, T z1, T z2) {
+#pragma clang fp contract(off)
+    return xy + fm(k.w2z, z2, k.w1z * z1);
+}
+
+// psi forcing of eq. (rhs) without its stencil term, for S_psi = Y_psi + h G:
+//   g = c Lap + S (mu2 - lambda S^2) - 3 Y_psi - 3 h G
+// base = S (mu2 - lambda S^2) - 3 Y_psi
+template <typename T>
+__device__ __forceinline__ T force_base(const PointCoef<T>& k, T S, T ypsi) {
+#pragma clang fp contract(off)
+    const T m = fm(-k.lam, S * S, k.mu2);
+    return fm(S, m, T(-3) * ypsi);
+}
+
+// S_phi of stages 2, 3, 4 from Y and the previous G (section 2.1, RK4 stages)
+template <typename T>
+__device__ __forceinline__ T s_phi2(const PointCoef<T>& k, T yp, T ys) {
+    return fm(k.hdt, ys, yp);
+}
+template <typename T>
+__device__ __forceinline__ T s_phi3(const PointCoef<T>& k, T yp, T ys, T g1) {
+    return fm(k.hdt, fm(k.hdt, g1, ys), yp);
+}
+template <typename T>
+__device__ __forceinline__ T s_phi4(const PointCoef<T>& k, T yp, T ys, T g2) {
+    return fm(k.dt, fm(k.hdt, g2, ys), yp);
+}
+
+// classical RK4 update from the state (p, s) and the four psi derivatives:
+//   phi' = p + dt/6 (s + 2 k2 + 2 k3 + k4),  k_j = s + c_j dt G_{j-1}
+//   psi' = s + dt/6 (G1 + 2 G2 + 2 G3 + G4)
+struct Upd {
+    double p, s;
+};
+__device__ __forceinline__ Upd rk4_update(double p, double s, double e1, double e2, double e3,
+                                         double e4, double hd, double dd, double dt6) {
+#pragma clang fp contract(off)
+    const double k2 = fm(hd, e1, s), k3 = fm(hd, e2, s), k4 = fm(dd, e3, s);
+    Upd u;
+    u.p = fm(dt6, fm(2.0, k2 + k3, s + k4), p);
+    u.s = fm(dt6, fm(2.0, e2 + e3, e1 + e4), s);
+    return u;
+}
+
 template <typename T, int STAGE, bool COMP>
 struct OwnRec {
     T p, s, g1, g2, g3;
@@ -131,11 +219,7 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
     const int nx = d->nx, ny = d->ny;
 
     const T c = (T)ldg(d->ctab, 4 * n + (STAGE - 1), true);
-    const T w0 = (T)d->w0;
-    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
-    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
-    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
-    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+    const PointCoef<T> K = point_coef<T>(d);
 
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
@@ -199,9 +283,9 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
     };
     auto formS = [&](T p, T s, T g) -> T {
         if constexpr (STAGE == 1) return p;
-        if constexpr (STAGE == 2) return p + hdt * s;
-        if constexpr (STAGE == 3) return p + hdt * (s + hdt * g);
-        return p + dtT * (s + hdt * g);
+        if constexpr (STAGE == 2) return s_phi2(K, p, s);
+        if constexpr (STAGE == 3) return s_phi3(K, p, s, g);
+        return s_phi4(K, p, s, g);
     };
     auto formS_own = [&](const Rec& r) -> T {
         return formS(r.p, r.s, (STAGE == 3) ? r.g1 : r.g2);
@@ -227,49 +311,39 @@ stage_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles
 
         const T(*P)[LX] = sm[buf];
         const int lx = tx + 2, ly = ty + 2;
-        T lap = w0 * q2;
-        lap += w1x * (P[ly][lx - 1] + P[ly][lx + 1]);
-        lap += w2x * (P[ly][lx - 2] + P[ly][lx + 2]);
-        lap += w1y * (P[ly - 1][lx] + P[ly + 1][lx]);
-        lap += w2y * (P[ly - 2][lx] + P[ly + 2][lx]);
-        lap += w1z * (q1 + q3);
-        lap += w2z * (q0 + q4);
+        const T lap = lap_z(K,
+                            lap_xy(K, q2, P[ly][lx - 1] + P[ly][lx + 1], P[ly][lx - 2] + P[ly][lx + 2],
+                                   P[ly - 1][lx] + P[ly + 1][lx], P[ly - 2][lx] + P[ly + 2][lx]),
+                            q1 + q3, q0 + q4);
 
-        // centre: S_psi,s and the psi forcing g = -3 S_psi + c Lap + mu2 S - lambda S^3
-        T spsi;
-        if constexpr (STAGE == 1) spsi = r0.s;
-        if constexpr (STAGE == 2) spsi = r0.s + hdt * r0.g1;
-        if constexpr (STAGE == 3) spsi = r0.s + hdt * r0.g2;
-        if constexpr (STAGE == 4) spsi = r0.s + dtT * r0.g3;
-        const T S = q2;
-        const T g = -T(3) * spsi + c * lap + mu2 * S - lam * S * S * S;
+        // centre: G_s = c Lap + S (mu2 - lambda S^2) - 3 S_psi,s with
+        // S_psi,s = Y_psi + h G_{s-1}
+        const T base = force_base(K, q2, r0.s);
+        T g;
+        if constexpr (STAGE == 1) g = fm(c, lap, base);
+        if constexpr (STAGE == 2) g = fm(c, lap, fm(K.m3h, r0.g1, base));
+        if constexpr (STAGE == 3) g = fm(c, lap, fm(K.m3h, r0.g2, base));
+        if constexpr (STAGE == 4) g = fm(c, lap, fm(K.m3d, r0.g3, base));
 
         const long long o = (long long)z * sz + own_off;
         if (own_st) {
             if constexpr (STAGE < 4) {
                 stg((T*)d->g[STAGE - 1], o, g);
             } else if constexpr (!COMP) {
-                const double dt6 = d->dt6;
-                const T k2 = r0.s + hdt * r0.g1;
-                const T k3 = r0.s + hdt * r0.g2;
-                stg((T*)d->y_phi[par ^ 1], o, (T)(r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi)));
-                stg((T*)d->y_psi[par ^ 1], o,
-                    (T)(r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * r0.g3 + g)));
+                const Upd u = rk4_update(r0.p, r0.s, r0.g1, r0.g2, r0.g3, g, d->hdt, d->dt, d->dt6);
+                stg((T*)d->y_phi[par ^ 1], o, (T)u.p);
+                stg((T*)d->y_psi[par ^ 1], o, (T)u.s);
             } else {
                 // compensated state: v = hi + lo carried in FP64 registers;
                 // the stage derivatives come from the FP32 stage arithmetic
-                const double hd = d->hdt, dd = d->dt, dt6 = d->dt6;
                 const double p = (double)r0.p + (double)r0.lp;
                 const double s = (double)r0.s + (double)r0.ls;
-                const double a1 = r0.g1, a2 = r0.g2, a3 = r0.g3, a4 = g;
-                const double k2 = s + hd * a1, k3 = s + hd * a2, k4 = s + dd * a3;
-                const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
-                const double ns_ = s + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
-                const float hp = (float)np_, hs = (float)ns_;
+                const Upd u = rk4_update(p, s, r0.g1, r0.g2, r0.g3, g, d->hdt, d->dt, d->dt6);
+                const float hp = (float)u.p, hs = (float)u.s;
                 stg((float*)d->y_phi[par ^ 1], o, hp);
                 stg((float*)d->y_psi[par ^ 1], o, hs);
-                stg(d->lo_phi, o, (float)(np_ - (double)hp));
-                stg(d->lo_psi, o, (float)(ns_ - (double)hs));
+                stg(d->lo_phi, o, (float)(u.p - (double)hp));
+                stg(d->lo_psi, o, (float)(u.s - (double)hs));
             }
         }
         q0 = q1; q1 = q2; q2 = q3; q3 = q4;
@@ -314,11 +388,7 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 
     const T ca = (T)ldg(d->ctab, 4 * n + 2 * PAIR, true);
     const T cb = (T)ldg(d->ctab, 4 * n + 2 * PAIR + 1, true);
-    const T w0 = (T)d->w0;
-    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
-    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
-    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
-    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+    const PointCoef<T> K = point_coef<T>(d);
 
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
@@ -366,11 +436,11 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     // the two stencil inputs: PAIR 0: S_phi,1 and S_phi,2; PAIR 1: S_phi,3 and S_phi,4
     auto formA = [&](const Rec& r) -> T {
         if constexpr (PAIR == 0) return r.p;
-        return r.p + hdt * (r.s + hdt * r.g1);
+        return s_phi3(K, r.p, r.s, r.g1);
     };
     auto formB = [&](const Rec& r) -> T {
-        if constexpr (PAIR == 0) return r.p + hdt * r.s;
-        return r.p + dtT * (r.s + hdt * r.g2);
+        if constexpr (PAIR == 0) return s_phi2(K, r.p, r.s);
+        return s_phi4(K, r.p, r.s, r.g2);
     };
 
     const int z0 = tl.z0, z1 = tl.z1;
@@ -409,61 +479,42 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         const int lx = tx + 2, ly = ty + 2;
         const T(*PA)[LX] = sa[buf];
         const T(*PB)[LX] = sb[buf];
-        T lapA = w0 * a2;
-        lapA += w1x * (PA[ly][lx - 1] + PA[ly][lx + 1]);
-        lapA += w2x * (PA[ly][lx - 2] + PA[ly][lx + 2]);
-        lapA += w1y * (PA[ly - 1][lx] + PA[ly + 1][lx]);
-        lapA += w2y * (PA[ly - 2][lx] + PA[ly + 2][lx]);
-        lapA += w1z * (a1 + a3);
-        lapA += w2z * (a0 + a4);
-        T lapB = w0 * b2;
-        lapB += w1x * (PB[ly][lx - 1] + PB[ly][lx + 1]);
-        lapB += w2x * (PB[ly][lx - 2] + PB[ly][lx + 2]);
-        lapB += w1y * (PB[ly - 1][lx] + PB[ly + 1][lx]);
-        lapB += w2y * (PB[ly - 2][lx] + PB[ly + 2][lx]);
-        lapB += w1z * (b1 + b3);
-        lapB += w2z * (b0 + b4);
+        const T lapA = lap_z(K,
+                             lap_xy(K, a2, PA[ly][lx - 1] + PA[ly][lx + 1], PA[ly][lx - 2] + PA[ly][lx + 2],
+                                    PA[ly - 1][lx] + PA[ly + 1][lx], PA[ly - 2][lx] + PA[ly + 2][lx]),
+                             a1 + a3, a0 + a4);
+        const T lapB = lap_z(K,
+                             lap_xy(K, b2, PB[ly][lx - 1] + PB[ly][lx + 1], PB[ly][lx - 2] + PB[ly][lx + 2],
+                                    PB[ly - 1][lx] + PB[ly + 1][lx], PB[ly - 2][lx] + PB[ly + 2][lx]),
+                             b1 + b3, b0 + b4);
 
         const long long o = (long long)z * sz + own_off;
         if constexpr (PAIR == 0) {
             // stage 1: S_psi,1 = Y_psi;  stage 2: S_psi,2 = Y_psi + dt/2 G1
-            const T SA = a2, SB = b2;
-            const T g1 = -T(3) * r0.s + ca * lapA + mu2 * SA - lam * SA * SA * SA;
-            const T spsi2 = r0.s + hdt * g1;
-            const T g2 = -T(3) * spsi2 + cb * lapB + mu2 * SB - lam * SB * SB * SB;
+            const T g1 = fm(ca, lapA, force_base(K, a2, r0.s));
+            const T g2 = fm(cb, lapB, fm(K.m3h, g1, force_base(K, b2, r0.s)));
             if (own_st) {
                 stg((T*)d->g[0], o, g1);
                 stg((T*)d->g[1], o, g2);
             }
         } else {
             // stage 3: S_psi,3 = Y_psi + dt/2 G2;  stage 4: S_psi,4 = Y_psi + dt G3
-            const T SA = a2, SB = b2;
-            const T spsi3 = r0.s + hdt * r0.g2;
-            const T g3 = -T(3) * spsi3 + ca * lapA + mu2 * SA - lam * SA * SA * SA;
-            const T spsi4 = r0.s + dtT * g3;
-            const T g4 = -T(3) * spsi4 + cb * lapB + mu2 * SB - lam * SB * SB * SB;
+            const T g3 = fm(ca, lapA, fm(K.m3h, r0.g2, force_base(K, a2, r0.s)));
+            const T g4 = fm(cb, lapB, fm(K.m3d, g3, force_base(K, b2, r0.s)));
             if (own_st) {
                 if constexpr (!COMP) {
-                    const double dt6 = d->dt6;
-                    const T k2 = r0.s + hdt * r0.g1;
-                    const T k3 = r0.s + hdt * r0.g2;
-                    stg((T*)d->y_phi[par ^ 1], o,
-                        (T)(r0.p + dt6 * (r0.s + T(2) * k2 + T(2) * k3 + spsi4)));
-                    stg((T*)d->y_psi[par ^ 1], o,
-                        (T)(r0.s + dt6 * (r0.g1 + T(2) * r0.g2 + T(2) * g3 + g4)));
+                    const Upd u = rk4_update(r0.p, r0.s, r0.g1, r0.g2, g3, g4, d->hdt, d->dt, d->dt6);
+                    stg((T*)d->y_phi[par ^ 1], o, (T)u.p);
+                    stg((T*)d->y_psi[par ^ 1], o, (T)u.s);
                 } else {
-                    const double hd = d->hdt, dd = d->dt, dt6 = d->dt6;
                     const double p = (double)r0.p + (double)lp;
                     const double s = (double)r0.s + (double)ls;
-                    const double e1 = r0.g1, e2 = r0.g2, e3 = g3, e4 = g4;
-                    const double k2 = s + hd * e1, k3 = s + hd * e2, k4 = s + dd * e3;
-                    const double np_ = p + dt6 * (s + 2.0 * k2 + 2.0 * k3 + k4);
-                    const double ns_ = s + dt6 * (e1 + 2.0 * e2 + 2.0 * e3 + e4);
-                    const float hp = (float)np_, hs = (float)ns_;
+                    const Upd u = rk4_update(p, s, r0.g1, r0.g2, g3, g4, d->hdt, d->dt, d->dt6);
+                    const float hp = (float)u.p, hs = (float)u.s;
                     stg((float*)d->y_phi[par ^ 1], o, hp);
                     stg((float*)d->y_psi[par ^ 1], o, hs);
-                    stg(d->lo_phi, o, (float)(np_ - (double)hp));
-                    stg(d->lo_psi, o, (float)(ns_ - (double)hs));
+                    stg(d->lo_phi, o, (float)(u.p - (double)hp));
+                    stg(d->lo_psi, o, (float)(u.s - (double)hs));
                 }
             }
         }
@@ -477,10 +528,9 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 }
 
 // Whole-step kernel: all four stages of one RK4 step in one z-march.
-// A block owns an interior tile of (RX-4) x 12 columns; its RX*16 threads own
-// the RX x 16 columns of the tile plus a 2-cell ring (region R2).  RX = 64
-// (1024 threads, one block per CU) or 32 (512 threads, two blocks per CU).
-// Per plane zi:
+// A block's RX*RY threads own the RX x RY columns (region R2) of an interior
+// tile of (RX-4) x (RY-4) columns plus a 2-cell ring; the shapes in use are
+// listed with the launcher.  Per plane zi:
 //   stage 1+2 on R2: G1, G2 at plane zi from the stencils of Y_phi and S_phi,2
 //     (x-y part from an LDS plane over the 4-cell ring R4, z part from each
 //     thread's register queue of Y planes zi-2..zi+2); outside the grid
@@ -491,18 +541,18 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 //     the queues and the thread's own Y and G1, G2 (2-plane delay).
 // HBM traffic is Y in and Y' out (4 field passes per step); the ring columns'
 // G1, G2 are recomputed by neighbouring blocks instead of stored.  The
-// per-point arithmetic and its order are those of the stage-pair kernels, so
-// results are bitwise equal to them.  One barrier per plane: the stage-1+2
-// plane is double-buffered, and stages 3+4 read ring slots written two
-// planes earlier.  All per-plane queues are rings indexed by the plane number
+// per-point arithmetic is the shared one above, so results are bitwise equal
+// to the other schemes.  One barrier per plane: the stage-1+2 plane is
+// double-buffered, and stages 3+4 read ring slots written two planes
+// earlier.  All per-plane queues are rings indexed by the plane number
 // modulo 6 and the loop is unrolled by 6, so queue shifts are register
 // renaming rather than moves.
-constexpr int SK_RY = 16;
-
-// 32-wide blocks: two resident 8-wave blocks per CU = 4 waves per SIMD
-// (the second launch-bounds argument is the minimum waves per SIMD)
-template <typename T, bool COMP, int SK_RX>
-__global__ void __launch_bounds__(SK_RX * SK_RY, SK_RX == 32 ? 4 : 1)
+//
+// Every shape runs 4 waves per SIMD (the second launch-bounds argument is the
+// minimum waves per SIMD, which caps registers at 128): 16-wave blocks, one
+// per CU.
+template <typename T, bool COMP, int SK_RX, int SK_RY>
+__global__ void __launch_bounds__(SK_RX * SK_RY, 4)
 step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
             long long kstep) {
     constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
@@ -528,11 +578,7 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 
     const T c1 = (T)ldg(d->ctab, 4 * n + 0, true), c2 = (T)ldg(d->ctab, 4 * n + 1, true);
     const T c3 = (T)ldg(d->ctab, 4 * n + 2, true), c4 = (T)ldg(d->ctab, 4 * n + 3, true);
-    const T w0 = (T)d->w0;
-    const T w1x = (T)d->w1[0], w1y = (T)d->w1[1], w1z = (T)d->w1[2];
-    const T w2x = (T)d->w2[0], w2y = (T)d->w2[1], w2z = (T)d->w2[2];
-    const T mu2 = (T)d->mu2, lam = (T)d->lambda;
-    const T dtT = (T)d->dt, hdt = (T)d->hdt;
+    const PointCoef<T> K = point_coef<T>(d);
     const double dt6 = d->dt6, hdd = d->hdt, dtd = d->dt;
 
     const int tid = threadIdx.x;
@@ -652,11 +698,12 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 
         // ---- stages 1 + 2 at plane zi over R2 ----
         const T yp0 = qp[Q(0)], ys0 = qs[Q(0)];
+        const T sb0 = s_phi2(K, yp0, ys0);
         pa[B][ry + 2][rx + 2] = yp0;
-        pb[B][ry + 2][rx + 2] = yp0 + hdt * ys0;
+        pb[B][ry + 2][rx + 2] = sb0;
         if (has_outer) {
             pa[B][oy][ox] = opr[OS];
-            pb[B][oy][ox] = opr[OS] + hdt * osr[OS];
+            pb[B][oy][ox] = s_phi2(K, opr[OS], osr[OS]);
         }
         // the only barrier of the plane: it publishes this plane's stage-1+2
         // inputs and the ring slot written two planes ago (read below)
@@ -667,28 +714,21 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             const int lx = rx + 2, ly = ry + 2;
             const T(*A)[SK_QX] = pa[B];
             const T(*Bp)[SK_QX] = pb[B];
-            const T SA = yp0, SB = yp0 + hdt * ys0;
-            T lapA = w0 * SA;
-            lapA += w1x * (A[ly][lx - 1] + A[ly][lx + 1]);
-            lapA += w2x * (A[ly][lx - 2] + A[ly][lx + 2]);
-            lapA += w1y * (A[ly - 1][lx] + A[ly + 1][lx]);
-            lapA += w2y * (A[ly - 2][lx] + A[ly + 2][lx]);
-            lapA += w1z * (qp[Q(-1)] + qp[Q(1)]);
-            lapA += w2z * (qp[Q(-2)] + qp[Q(2)]);
-            T lapB = w0 * SB;
-            lapB += w1x * (Bp[ly][lx - 1] + Bp[ly][lx + 1]);
-            lapB += w2x * (Bp[ly][lx - 2] + Bp[ly][lx + 2]);
-            lapB += w1y * (Bp[ly - 1][lx] + Bp[ly + 1][lx]);
-            lapB += w2y * (Bp[ly - 2][lx] + Bp[ly + 2][lx]);
-            lapB += w1z * ((qp[Q(-1)] + hdt * qs[Q(-1)]) + (qp[Q(1)] + hdt * qs[Q(1)]));
-            lapB += w2z * ((qp[Q(-2)] + hdt * qs[Q(-2)]) + (qp[Q(2)] + hdt * qs[Q(2)]));
-            g1 = -T(3) * ys0 + c1 * lapA + mu2 * SA - lam * SA * SA * SA;
-            const T spsi2 = ys0 + hdt * g1;
-            g2 = -T(3) * spsi2 + c2 * lapB + mu2 * SB - lam * SB * SB * SB;
+            const T lapA = lap_z(K,
+                                 lap_xy(K, yp0, A[ly][lx - 1] + A[ly][lx + 1], A[ly][lx - 2] + A[ly][lx + 2],
+                                        A[ly - 1][lx] + A[ly + 1][lx], A[ly - 2][lx] + A[ly + 2][lx]),
+                                 qp[Q(-1)] + qp[Q(1)], qp[Q(-2)] + qp[Q(2)]);
+            const T lapB = lap_z(K,
+                                 lap_xy(K, sb0, Bp[ly][lx - 1] + Bp[ly][lx + 1], Bp[ly][lx - 2] + Bp[ly][lx + 2],
+                                        Bp[ly - 1][lx] + Bp[ly + 1][lx], Bp[ly - 2][lx] + Bp[ly + 2][lx]),
+                                 s_phi2(K, qp[Q(-1)], qs[Q(-1)]) + s_phi2(K, qp[Q(1)], qs[Q(1)]),
+                                 s_phi2(K, qp[Q(-2)], qs[Q(-2)]) + s_phi2(K, qp[Q(2)], qs[Q(2)]));
+            g1 = fm(c1, lapA, force_base(K, yp0, ys0));
+            g2 = fm(c2, lapB, fm(K.m3h, g1, force_base(K, sb0, ys0)));
         }
         // stage inputs of stages 3 and 4 at plane zi (zero outside the grid)
-        const T s3 = yp0 + hdt * (ys0 + hdt * g1);
-        const T s4 = yp0 + dtT * (ys0 + hdt * g2);
+        const T s3 = s_phi3(K, yp0, ys0, g1);
+        const T s4 = s_phi4(K, yp0, ys0, g2);
         a3q[Q(0)] = s3;
         a4q[Q(0)] = s4;
         g1r[Q(0)] = g1;
@@ -703,42 +743,32 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         float ol_p = 0.f, ol_s = 0.f;
         if (zout && own_st) {
             const T SA = a3q[Q(-2)], SB = a4q[Q(-2)];
-            T lapA = w0 * SA;
-            lapA += w1x * (r3[RS2][ry][rx - 1] + r3[RS2][ry][rx + 1]);
-            lapA += w2x * (r3[RS2][ry][rx - 2] + r3[RS2][ry][rx + 2]);
-            lapA += w1y * (r3[RS2][ry - 1][rx] + r3[RS2][ry + 1][rx]);
-            lapA += w2y * (r3[RS2][ry - 2][rx] + r3[RS2][ry + 2][rx]);
-            lapA += w1z * (a3q[Q(-3)] + a3q[Q(-1)]);
-            lapA += w2z * (a3q[Q(-4)] + a3q[Q(0)]);
-            T lapB = w0 * SB;
-            lapB += w1x * (r4[RS2][ry][rx - 1] + r4[RS2][ry][rx + 1]);
-            lapB += w2x * (r4[RS2][ry][rx - 2] + r4[RS2][ry][rx + 2]);
-            lapB += w1y * (r4[RS2][ry - 1][rx] + r4[RS2][ry + 1][rx]);
-            lapB += w2y * (r4[RS2][ry - 2][rx] + r4[RS2][ry + 2][rx]);
-            lapB += w1z * (a4q[Q(-3)] + a4q[Q(-1)]);
-            lapB += w2z * (a4q[Q(-4)] + a4q[Q(0)]);
+            const T(*R3)[SK_RX] = r3[RS2];
+            const T(*R4)[SK_RX] = r4[RS2];
+            const T lapA = lap_z(K,
+                                 lap_xy(K, SA, R3[ry][rx - 1] + R3[ry][rx + 1], R3[ry][rx - 2] + R3[ry][rx + 2],
+                                        R3[ry - 1][rx] + R3[ry + 1][rx], R3[ry - 2][rx] + R3[ry + 2][rx]),
+                                 a3q[Q(-3)] + a3q[Q(-1)], a3q[Q(-4)] + a3q[Q(0)]);
+            const T lapB = lap_z(K,
+                                 lap_xy(K, SB, R4[ry][rx - 1] + R4[ry][rx + 1], R4[ry][rx - 2] + R4[ry][rx + 2],
+                                        R4[ry - 1][rx] + R4[ry + 1][rx], R4[ry - 2][rx] + R4[ry + 2][rx]),
+                                 a4q[Q(-3)] + a4q[Q(-1)], a4q[Q(-4)] + a4q[Q(0)]);
             const T yp = qp[Q(-2)], ys = qs[Q(-2)], e1 = g1r[Q(-2)], e2 = g2r[Q(-2)];
-            const T spsi3 = ys + hdt * e2;
-            const T g3 = -T(3) * spsi3 + c3 * lapA + mu2 * SA - lam * SA * SA * SA;
-            const T spsi4 = ys + dtT * g3;
-            const T g4 = -T(3) * spsi4 + c4 * lapB + mu2 * SB - lam * SB * SB * SB;
+            const T g3 = fm(c3, lapA, fm(K.m3h, e2, force_base(K, SA, ys)));
+            const T g4 = fm(c4, lapB, fm(K.m3d, g3, force_base(K, SB, ys)));
             if constexpr (!COMP) {
-                const T k2 = ys + hdt * e1;
-                const T k3 = ys + hdt * e2;
-                op_ = (T)(yp + dt6 * (ys + T(2) * k2 + T(2) * k3 + spsi4));
-                os_ = (T)(ys + dt6 * (e1 + T(2) * e2 + T(2) * g3 + g4));
+                const Upd u = rk4_update(yp, ys, e1, e2, g3, g4, hdd, dtd, dt6);
+                op_ = (T)u.p;
+                os_ = (T)u.s;
             } else {
                 const double pp = (double)yp + (double)lpr[OS2];
                 const double ss = (double)ys + (double)lsr[OS2];
-                const double a1 = e1, a2 = e2, a3 = g3, a4 = g4;
-                const double k2 = ss + hdd * a1, k3 = ss + hdd * a2, k4 = ss + dtd * a3;
-                const double vp = pp + dt6 * (ss + 2.0 * k2 + 2.0 * k3 + k4);
-                const double vs = ss + dt6 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
-                const float hp = (float)vp, hs = (float)vs;
+                const Upd u = rk4_update(pp, ss, e1, e2, g3, g4, hdd, dtd, dt6);
+                const float hp = (float)u.p, hs = (float)u.s;
                 op_ = hp;
                 os_ = hs;
-                ol_p = (float)(vp - (double)hp);
-                ol_s = (float)(vs - (double)hs);
+                ol_p = (float)(u.p - (double)hp);
+                ol_s = (float)(u.s - (double)hs);
             }
         }
         // stores outside the branch: lanes and planes without output use an
@@ -987,18 +1017,25 @@ hipError_t launch_pair_t(int pair, const SolveDesc* descs, const Tile* tiles, in
     return hipGetLastError();
 }
 
-template <typename T, bool COMP>
-hipError_t launch_step_t(int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
-                         long long kstep, hipStream_t s) {
-    if (width == 64)
-        hipLaunchKernelGGL((step_kernel<T, COMP, 64>), dim3(ntiles), dim3(64 * SK_RY), 0, s, descs,
-                           tiles, ntiles, kstep);
-    else if (width == 32)
-        hipLaunchKernelGGL((step_kernel<T, COMP, 32>), dim3(ntiles), dim3(32 * SK_RY), 0, s, descs,
-                           tiles, ntiles, kstep);
-    else
-        return hipErrorInvalidValue;
+template <typename T, bool COMP, int RX, int RY>
+hipError_t launch_step_shape(const SolveDesc* descs, const Tile* tiles, int ntiles, long long kstep,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<T, COMP, RX, RY>), dim3(ntiles), dim3(RX * RY), 0, s, descs,
+                       tiles, ntiles, kstep);
     return hipGetLastError();
+}
+
+// region shapes, indexed as STEP_SHAPES in hb_internal.h
+template <typename T, bool COMP>
+hipError_t launch_step_t(int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
+                         long long kstep, hipStream_t s) {
+    static_assert(STEP_SHAPES[0].rx == 36 && STEP_SHAPES[0].ry == 28, "shape table");
+    static_assert(STEP_SHAPES[1].rx == 64 && STEP_SHAPES[1].ry == 16, "shape table");
+    switch (shape) {
+        case 0: return launch_step_shape<T, COMP, 36, 28>(descs, tiles, ntiles, kstep, s);
+        case 1: return launch_step_shape<T, COMP, 64, 16>(descs, tiles, ntiles, kstep, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -1038,13 +1075,13 @@ int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* 
     return (int)e;
 }
 
-int launch_step(int prec, int width, const SolveDesc* descs, const Tile* tiles, int ntiles,
+int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream) {
     if (ntiles <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = prec == PREC_F64
-                       ? launch_step_t<double, false>(width, descs, tiles, ntiles, kstep, s)
-                       : launch_step_t<float, true>(width, descs, tiles, ntiles, kstep, s);
+                       ? launch_step_t<double, false>(shape, descs, tiles, ntiles, kstep, s)
+                       : launch_step_t<float, true>(shape, descs, tiles, ntiles, kstep, s);
     return (int)e;
 }
 

@@ -75,7 +75,10 @@ Layout plan_layout(const hb_config& c) {
     const long long line = 128 / (long long)L.esz;  // elements per 128-byte line
     L.sy = round_up((long long)L.nx + 4, line);
     L.sz = L.sy * ((long long)L.ny + 4);
-    L.origin_off = 2 * L.sz + 2 * L.sy + line;
+    // cell (-2, y, z) starts a 128-byte line: a tile region that starts two
+    // cells before a multiple of the tile width (32 for the whole-step
+    // kernel) reads whole lines
+    L.origin_off = 2 * L.sz + 2 * L.sy + 2;
     const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
                            L.nx + 2;
     L.field_elems = round_up(last, 256 / (long long)L.esz);
@@ -381,26 +384,45 @@ int device_cus() {
     return cus;
 }
 
-// whole-step kernel: region width 64 (by = 16) or 32 (by = 8) columns
-int step_width(int by) { return by == 16 ? 64 : 32; }
+// whole-step kernel region shape (STEP_SHAPES): by = 8 selects 36 x 28
+// regions (32 x 24 tiles), by = 16 selects 64 x 16 regions (60 x 12 tiles).
+// Defaults, from timings of 256^3 and 512^3 grids: 36 x 28 for FP64, 64 x 16
+// for FP32c (whose halved LDS planes favour the wider rows).
+int step_shape(int by) { return by == 16 ? 1 : 0; }
+int default_step_by(int precision) { return precision == HB_F32C ? 16 : 8; }
 
-// 32-plane z-marches (4 warm-up planes), shorter only while one solve would
-// give fewer tiles than resident block slots; measured best on 256^3
+// z-march length for one solve.  Blocks run in rounds of (CUs x blocks per
+// CU); a march of zc planes costs about zc + 4 planes (warm-up) rounded up to
+// the unroll of 6, plus a fixed start-up.  Pick the zc that minimises
+// rounds x cost per block, so the last round is not mostly empty and the
+// warm-up planes stay a small share.  Batches keep 32-plane marches (their
+// many tiles already fill the rounds).
 int default_zc_step(const Layout& L, int by, int nmembers) {
     if (nmembers > 1) return std::min(L.nz, 32);
-    const int tx = step_width(by) - 4;
-    const long long xy = (long long)((L.nx + tx - 1) / tx) * ((L.ny + STEP_TILE_Y - 1) / STEP_TILE_Y);
-    const long long slots = (long long)device_cus() * (step_width(by) == 32 ? 2 : 1);
-    int zc = std::min(L.nz, 32);
-    while (zc > 8 && xy * ((L.nz + zc - 1) / zc) < slots) zc = (zc + 1) / 2;
-    return zc;
+    const StepShape sh = STEP_SHAPES[step_shape(by)];
+    const long long tx = sh.rx - 4, ty = sh.ry - 4;
+    const long long xy = ((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
+    const long long slots = (long long)device_cus() * sh.blocks_per_cu;
+    int best = std::min(L.nz, 32);
+    double best_cost = 1e300;
+    for (int zc = std::min(L.nz, 8); zc <= L.nz; ++zc) {
+        const long long chunks = (L.nz + zc - 1) / zc;
+        const long long rounds = (xy * chunks + slots - 1) / slots;
+        const int planes = (zc + 4 + 5) / 6 * 6;
+        const double cost = (double)rounds * (planes + 3);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return best;
 }
 
 void make_tiles(const Solve& s, int solve_index, int scheme, int by, int zc_req, int nmembers,
                 std::vector<Tile>& out) {
     const Layout& L = s.L;
-    const int tx = scheme == SCHEME_STEP ? step_width(by) - 4 : TILE_X;
-    const int ty = scheme == SCHEME_STEP ? STEP_TILE_Y : by;
+    const int tx = scheme == SCHEME_STEP ? STEP_SHAPES[step_shape(by)].rx - 4 : TILE_X;
+    const int ty = scheme == SCHEME_STEP ? STEP_SHAPES[step_shape(by)].ry - 4 : by;
     const int zc = zc_req > 0 ? zc_req
                               : (scheme == SCHEME_STEP ? default_zc_step(L, by, nmembers)
                                                        : default_zc(L, by));
@@ -467,7 +489,7 @@ int kernels_per_step(const Group& g) {
 // kernel i of one step (the whole step, stage pair i, or stage i+1)
 int launch_step_kernel(const Group& g, int i, long long kstep, hipStream_t stream) {
     if (g.scheme == SCHEME_STEP)
-        return from_hip(launch_step(g.prec, step_width(g.by), g.d_desc, g.d_tiles, g.ntiles, kstep,
+        return from_hip(launch_step(g.prec, step_shape(g.by), g.d_desc, g.d_tiles, g.ntiles, kstep,
                                     stream),
                         "step launch");
     if (g.scheme == SCHEME_STAGES)
@@ -615,7 +637,7 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
     h->g.scheme = scheme_of(cfg->flags);
-    h->g.by = h->g.scheme == SCHEME_STEP ? 8 : DEFAULT_BY;
+    h->g.by = h->g.scheme == SCHEME_STEP ? default_step_by(cfg->precision) : DEFAULT_BY;
     h->g.members.push_back(h->s.get());
     HIP_TRY(hipStreamSynchronize(h->stream));
     *out = h.release();
@@ -943,7 +965,7 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
         if (i == 0)
             for (Group& g : b->groups) {
                 g.scheme = scheme_of(cfgs[i].flags);
-                g.by = g.scheme == SCHEME_STEP ? 8 : DEFAULT_BY;
+                g.by = g.scheme == SCHEME_STEP ? default_step_by(g.prec) : DEFAULT_BY;
             }
         b->use_graph = b->use_graph || (cfgs[i].flags & HB_USE_GRAPH);
         b->solves.push_back(std::move(s));
@@ -1060,7 +1082,7 @@ int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out
     }
     p->groups[0].prec = HB_F64;
     p->groups[1].prec = HB_F32C;
-    for (Group& g : p->groups) g.by = 8;  // whole-step scheme, 32-wide blocks
+    for (Group& g : p->groups) g.by = default_step_by(g.prec);  // whole-step scheme
     *out = p.release();
     return HB_OK;
 }
