@@ -57,8 +57,8 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # step_kernel_cube256.md), each scaled by the counter's reading for the plain
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel source they were measured on; any other source reports null.
-TRAFFIC_KERNEL_SHA = "3b782f75fab88eea"
-TRAFFIC_BYTES_F64 = 647.7 * 2 ** 20
+TRAFFIC_KERNEL_SHA = "9f871dc45f694d37"
+TRAFFIC_BYTES_F64 = 621.8 * 2 ** 20
 
 
 def kernel_source_sha():
