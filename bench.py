@@ -188,6 +188,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-count", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated arrival rates (req/s): also run a trace of "
+                         "--serve-sweep-count arrivals at each (latency knee)")
+    ap.add_argument("--serve-sweep-count", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", action="store_true")
     ap.add_argument("--probe", action="store_true",
@@ -255,6 +259,14 @@ def main():
         out["batched"] = run_batch(args.batch_count, args.batch_steps, 16)
     if not args.no_serve:
         out["served"] = run_serve(args.serve_count, args.serve_rate, 192.0)
+    if args.serve_sweep:
+        out["serve_sweep"] = []
+        for rate in (float(r) for r in args.serve_sweep.split(",")):
+            out["serve_sweep"].append(run_serve(args.serve_sweep_count, rate, 192.0))
+            r = out["serve_sweep"][-1]
+            print(f"serve sweep: {rate} req/s: p50 {r['p50_latency_s']:.3f} s, "
+                  f"p99 {r['p99_latency_s']:.3f} s, {r['solves_per_s']:.2f} solves/s",
+                  file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
