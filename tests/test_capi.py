@@ -41,3 +41,16 @@ def test_footprint_is_host_only(lib):
     assert hb.hb_footprint(c32) < fp
     bad = hb.make_config((0, 4, 4), (-1,) * 3, (1,) * 3, 1.0, 1.0, 0.01)
     assert hb.hb_footprint(bad) == 0
+
+
+def test_plane_size_limit_is_rejected(lib):
+    """A plane is addressed with 32-bit byte offsets: an x-y plane of 2 GiB or
+    more is rejected before anything is allocated (footprint 0, message)."""
+    from paper_1803_01291_amd import hb
+    ok = hb.make_config((16380, 16380, 1), (-1,) * 3, (1,) * 3, 1.0, 1.0, 1e-9,
+                        flags=hb.HB_ALLOW_UNSTABLE, precision=hb.HB_F32C)
+    assert hb.hb_footprint(ok) > 0          # 16384 x 16384 x 4 B = 1 GiB per plane
+    big = hb.make_config((16380, 16380, 1), (-1,) * 3, (1,) * 3, 1.0, 1.0, 1e-9,
+                         flags=hb.HB_ALLOW_UNSTABLE)
+    assert hb.hb_footprint(big) == 0        # FP64: 2 GiB per plane
+    assert "2 GiB" in hb.hb_last_error()

@@ -29,12 +29,16 @@ def test_config1_full(hb, oracle_mod):
     assert err <= TOL64
 
 
+# Whole-step kernel tiles (the default scheme): 32 x 24 (by 8) and 60 x 12
+# (by 16); tiling (by, zc), zc = 0 for the library's z-march length.
 @pytest.mark.parametrize("shape,tiling", [
-    ((70, 21, 13), None),          # 2 x-tiles (64 + 6), ragged y, default z
-    ((130, 17, 40), (8, 7)),       # 3 x-tiles, ragged z-chunks of 7
-    ((64, 32, 24), (16, 5)),       # exact x tile, BY = 16
-    ((200, 9, 11), (16, 0)),       # BY larger than a ragged y tail
+    ((70, 21, 13), None),          # 3 x-tiles (32 + 32 + 6), one ragged y-tile
+    ((130, 17, 40), (8, 7)),       # 5 x-tiles (ragged 2), z-marches of 7 (ragged 5)
+    ((64, 32, 24), (16, 5)),       # 2 x-tiles of 60 (ragged 4), 3 y-tiles (ragged 8)
+    ((200, 9, 11), (16, 0)),       # a y extent below one tile
     ((5, 3, 30), (8, 4)),          # narrower than one tile
+    ((97, 53, 41), (8, 0)),        # 4 x 3 tiles, every axis ragged (1, 5, z)
+    ((125, 50, 29), (16, 9)),      # 3 x 5 tiles of 60 x 12, ragged in all axes
 ])
 def test_ragged_shapes(hb, oracle_mod, shape, tiling):
     w = si.small_case(*shape, seed=sum(shape), steps=12)
