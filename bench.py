@@ -56,15 +56,18 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (profiles/
 # step_kernel_cube256.md), each scaled by the counter's reading for the plain
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
-# kernel source they were measured on; any other source reports null.
-TRAFFIC_KERNEL_SHA = "9f871dc45f694d37"
-TRAFFIC_BYTES_F64 = 621.8 * 2 ** 20
+# kernel and runtime sources they were measured on (the runtime picks the
+# tiling); any other source reports null.
+TRAFFIC_SOURCE_SHA = "4a2681becf7f6a45"
+TRAFFIC_BYTES_F64 = 626.5 * 2 ** 20
 
 
-def kernel_source_sha():
+def source_sha():
     import hashlib
-    p = os.path.join(ROOT, "paper_1803_01291_amd", "csrc", "hb_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("hb_kernels.hip", "hb_runtime.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1803_01291_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def run_gpu(w, precision, steps, warmup, timed_stage_steps):
@@ -232,7 +235,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (TRAFFIC_BYTES_F64
-                                 if kernel_source_sha() == TRAFFIC_KERNEL_SHA and args.n == 256
+                                 if source_sha() == TRAFFIC_SOURCE_SHA and args.n == 256
                                  else None),
                      "kernel": "step_kernel (whole RK4 step)",
                      "kernel_ms": kernel_ms,

@@ -154,8 +154,8 @@ int hb_diagnostics(hb_solver* s, hb_diag* out);
  * whole-step kernel, the length that best fills whole rounds of resident
  * blocks on the device); by in {8, 16}: rows of 64 columns per tile for the
  * stage-pair and per-stage kernels (default 16); for the whole-step kernel
- * by = 8 selects 32 x 24 tiles (1008-thread blocks; the FP64 default) and
- * by = 16 selects 60 x 12 tiles (1024-thread blocks; the FP32c default).
+ * by = 8 selects 32 x 24 tiles (1008-thread blocks) and by = 16 selects
+ * 60 x 12 tiles (1024-thread blocks; the default).
  * Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 

@@ -386,10 +386,10 @@ int device_cus() {
 
 // whole-step kernel region shape (STEP_SHAPES): by = 8 selects 36 x 28
 // regions (32 x 24 tiles), by = 16 selects 64 x 16 regions (60 x 12 tiles).
-// Defaults, from timings of 256^3 and 512^3 grids: 36 x 28 for FP64, 64 x 16
-// for FP32c (whose halved LDS planes favour the wider rows).
+// Default 64 x 16: on 256^3 and 512^3 grids, FP64 and FP32c, it was as fast
+// or 5-13% faster on every device measured.
 int step_shape(int by) { return by == 16 ? 1 : 0; }
-int default_step_by(int precision) { return precision == HB_F32C ? 16 : 8; }
+int default_step_by(int) { return 16; }
 
 // z-march length for one solve.  Blocks run in rounds of (CUs x blocks per
 // CU); a march of zc planes costs about zc + 4 planes (warm-up) rounded up to
