@@ -58,8 +58,8 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "4a2681becf7f6a45"
-TRAFFIC_BYTES_F64 = 626.5 * 2 ** 20
+TRAFFIC_SOURCE_SHA = "b351b99a6dcb3903"
+TRAFFIC_BYTES_F64 = 626.2 * 2 ** 20
 
 
 def source_sha():
@@ -70,13 +70,13 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def run_gpu(w, precision, steps, warmup, timed_stage_steps):
+def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0):
     import numpy as np
     import torch
     from paper_1803_01291_amd import hb
 
     p0, p1 = w.initial()
-    h = hb.hb_create(hb.config_from_workload(w, precision))
+    h = hb.hb_create(hb.config_from_workload(w, precision, flags))
     try:
         hb.hb_set_initial(h, p0, p1)
         hb.hb_step(h, warmup)
@@ -165,6 +165,56 @@ def run_serve(count, rate, budget_gb):
             "span_s": res["span_s"]}
 
 
+# radial batch kernel: LDS bytes per node-step (reads + writes of its LDS
+# arrays over the four stages: 39 reads and 9 writes of 8 B) and the LDS
+# peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
+RADIAL_LDS_BYTES = 48 * 8
+LDS_PEAK_GBS = 128 * 256 * 2.4
+
+
+def run_radial(count, m, steps, cpu_sample):
+    """A radial parameter sweep (section 2.2 form): `count` solves of `m`
+    nodes advanced `steps` RK4 steps in one launch, state resident in HBM;
+    the radial oracle timed on `cpu_sample` of the same solves."""
+    import torch
+    import synth_inputs as si
+    from paper_1803_01291_amd import hb
+    dr, dt, inv_L2 = 5e-4, 1e-4, 1 / 25
+    phi0, phi1, params = si.radial_sweep(count, m, dr)
+    cfgs = [hb.make_radial_config(m, dr, mu2, lam, dt, steps, 0.0, inv_L2) for mu2, lam in params]
+    dev = torch.device("cuda")
+    phi = torch.from_numpy(phi0).to(dev)
+    psi = torch.from_numpy(phi1).to(dev)
+    warm = [hb.make_radial_config(m, dr, mu2, lam, dt, 10, 0.0, inv_L2) for mu2, lam in params]
+    hb.hb_radial_solve(warm, phi.clone(), psi.clone())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb.hb_radial_solve(cfgs, phi, psi)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    node_steps = count * m * steps
+    rate = node_steps / sec
+    achieved = RADIAL_LDS_BYTES * rate / 1e9
+    cpu = None
+    if cpu_sample > 0:
+        from oracle.radial import radial_solve
+        t1 = time.perf_counter()
+        for i in range(cpu_sample):
+            mu2, lam = params[i]
+            radial_solve(phi0[i * m:(i + 1) * m], phi1[i * m:(i + 1) * m], dr, mu2, lam, dt,
+                         steps, t0=0.0, inv_L2=inv_L2)
+        cpu_sec = time.perf_counter() - t1
+        cpu = {"value": cpu_sample * m * steps / cpu_sec, "unit": "node-updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{cpu_sample} of the solves, NumPy radial oracle, {cpu_sec:.1f} s"}
+    return {"solves": count, "nodes": m, "steps": steps, "seconds": sec,
+            "solves_per_s": count / sec, "node_updates_per_s": rate,
+            "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS,
+                         "bytes_per_node_step": RADIAL_LDS_BYTES},
+            "cpu_baseline": cpu}
+
+
 def cpu_baseline(w, steps):
     import oracle
     p0, p1 = w.initial()
@@ -196,6 +246,12 @@ def main():
                          "--serve-sweep-count arrivals at each (latency knee)")
     ap.add_argument("--serve-sweep-count", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-radial", action="store_true")
+    ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
+                    help="3-D scheme of the single-solve legs: the whole-step kernel (default) "
+                         "or, for comparison, the stage-pair or per-stage kernels")
+    ap.add_argument("--radial-count", type=int, default=4096)
+    ap.add_argument("--radial-steps", type=int, default=2000)
     ap.add_argument("--forms", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="also measure the streamed-HBM ceiling (copy and 5-read/2-write probes)")
@@ -208,13 +264,18 @@ def main():
     import synth_inputs as si
     w = si.config2(n=args.n)
     N = w.points
-    elapsed, stage_ms, diag = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps)
-    kernel_ms = stage_ms[0]          # one whole-step kernel per step
+    from paper_1803_01291_amd import hb as _hb
+    flags = {"step": 0, "pairs": _hb.HB_PAIRWISE, "stages": _hb.HB_STAGEWISE}[args.scheme]
+    elapsed, stage_ms, diag = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps, flags)
+    # the whole-step kernel is one launch per step; the comparison schemes'
+    # kernels are summed over the step
+    kernel_ms = sum(stage_ms)
     rate = N * args.steps / elapsed
     # algorithmic bytes per launch: the per-point-step figure of the
     # measurement contract (152 B FP64 = 19 field passes) x interior points
     achieved = sum(STAGEWISE_BYTES[0]) * N / (kernel_ms * 1e-3) / 1e9
-    own = STEP_BYTES[0] * N / (kernel_ms * 1e-3) / 1e9
+    own_b = {"step": STEP_BYTES[0], "pairs": 80, "stages": sum(STAGEWISE_BYTES[0])}[args.scheme]
+    own = own_b * N / (kernel_ms * 1e-3) / 1e9
     step_alg = sum(STAGEWISE_BYTES[0]) * N
     out = {
         "metric": "RK4 grid-point updates/s (FP64, fused 13-point stencil stages)",
@@ -236,22 +297,25 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (TRAFFIC_BYTES_F64
                                  if source_sha() == TRAFFIC_SOURCE_SHA and args.n == 256
-                                 else None),
-                     "kernel": "step_kernel (whole RK4 step)",
+                                 and args.scheme == "step" else None),
+                     "kernel": {"step": "step_kernel (whole RK4 step)",
+                                "pairs": "pair_kernel x 2 (sum per step)",
+                                "stages": "stage_kernel x 4 (sum per step)"}[args.scheme],
                      "kernel_ms": kernel_ms,
                      "bytes_per_point": sum(STAGEWISE_BYTES[0]),
-                     "own_bytes_per_point": STEP_BYTES[0],
+                     "own_bytes_per_point": own_b,
                      "own_GBps": own, "own_frac": own / HBM_PEAK_GBS,
                      "step_alg_GBps": step_alg / (elapsed / args.steps) / 1e9,
                      "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
     }
     if args.forms:
-        e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps)
+        e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
+        k32 = sum(ms32)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
-                                 "kernel_ms": ms32[0],
-                                 "alg_GBps": sum(STAGEWISE_BYTES[1]) * N / (ms32[0] * 1e-3) / 1e9,
-                                 "own_GBps": STEP_BYTES[1] * N / (ms32[0] * 1e-3) / 1e9}}
+                                 "kernel_ms": k32,
+                                 "alg_GBps": sum(STAGEWISE_BYTES[1]) * N / (k32 * 1e-3) / 1e9,
+                                 "own_GBps": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9}}
     if args.probe:
         from paper_1803_01291_amd import hb
         gib = 1 << 30
@@ -270,6 +334,9 @@ def main():
             print(f"serve sweep: {rate} req/s: p50 {r['p50_latency_s']:.3f} s, "
                   f"p99 {r['p99_latency_s']:.3f} s, {r['solves_per_s']:.2f} solves/s",
                   file=sys.stderr, flush=True)
+    if not args.no_radial:
+        out["radial"] = run_radial(args.radial_count, 1000, args.radial_steps,
+                                   0 if args.no_cpu else 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

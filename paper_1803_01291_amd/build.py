@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhb.so")
-SOURCES = ["hb_kernels.hip", "hb_radial.hip", "hb_runtime.cpp"]
+SOURCES = ["hb_kernels.hip", "hb_diag.hip", "hb_radial.hip", "hb_runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

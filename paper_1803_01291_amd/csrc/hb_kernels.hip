@@ -885,85 +885,6 @@ __global__ void pack_kernel(D* __restrict__ dst, int nx, int ny, int nz, long lo
     }
 }
 
-// ---- diagnostics (FP64, deterministic) ----------------------------------------
-
-constexpr int DIAG_THREADS = 256;
-
-template <bool COMP>
-__device__ __forceinline__ double fld(const void* hi, const float* lo, long long o) {
-    if constexpr (COMP) return (double)ldg((const float*)hi, o, true) + (double)ldg(lo, o, true);
-    return ldg((const double*)hi, o, true);
-}
-
-// One block per (y, z) row group; per-thread partial sums in a fixed order,
-// then a fixed LDS tree.  Partials: DIAG_COUNT doubles per block.
-template <bool COMP>
-__global__ void __launch_bounds__(DIAG_THREADS)
-diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restrict__ partials) {
-    const int nx = d->nx, ny = d->ny, nz = d->nz;
-    const long long sy = d->sy, sz = d->sz;
-    const void* P = d->y_phi[par];
-    const void* S = d->y_psi[par];
-    const float* LP = d->lo_phi;
-    const float* LS = d->lo_psi;
-    const double w0 = d->w0, mu2 = d->mu2, lam = d->lambda;
-    double acc[DIAG_COUNT];
-    for (int k = 0; k < DIAG_COUNT; ++k) acc[k] = 0.0;
-    const long long rows = (long long)ny * nz;
-    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int y = (int)(row % ny), z = (int)(row / ny);
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const long long o = (long long)z * sz + (long long)y * sy + x;
-            const double p = fld<COMP>(P, LP, o);
-            const double s = fld<COMP>(S, LS, o);
-            double lap = w0 * p;
-            const long long st[3] = {1, sy, sz};
-            for (int a = 0; a < 3; ++a) {
-                lap += d->w1[a] * (fld<COMP>(P, LP, o - st[a]) + fld<COMP>(P, LP, o + st[a]));
-                lap += d->w2[a] * (fld<COMP>(P, LP, o - 2 * st[a]) + fld<COMP>(P, LP, o + 2 * st[a]));
-            }
-            acc[DIAG_SUM_PHI] += p;
-            acc[DIAG_SUM_PHI2] += p * p;
-            acc[DIAG_SUM_PSI2] += s * s;
-            acc[DIAG_MAX_PHI] = fmax(acc[DIAG_MAX_PHI], fabs(p));
-            acc[DIAG_MAX_PSI] = fmax(acc[DIAG_MAX_PSI], fabs(s));
-            acc[DIAG_MAX_LAP] = fmax(acc[DIAG_MAX_LAP], fabs(lap));
-            acc[DIAG_ENERGY] += 0.5 * s * s + 0.5 * c * p * (-lap) - 0.5 * mu2 * p * p +
-                                0.25 * lam * p * p * p * p;
-            acc[DIAG_NONFINITE] += (isfinite(p) ? 0.0 : 1.0) + (isfinite(s) ? 0.0 : 1.0);
-            acc[DIAG_NEGATIVE] += (p < 0.0) ? 1.0 : 0.0;
-        }
-    }
-    __shared__ double red[DIAG_THREADS];
-    for (int k = 0; k < DIAG_COUNT; ++k) {
-        red[threadIdx.x] = acc[k];
-        __syncthreads();
-        for (int w = DIAG_THREADS / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                const double a = red[threadIdx.x], b = red[threadIdx.x + w];
-                const bool is_max = (k == DIAG_MAX_PHI || k == DIAG_MAX_PSI || k == DIAG_MAX_LAP);
-                red[threadIdx.x] = is_max ? fmax(a, b) : a + b;
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partials[(long long)blockIdx.x * DIAG_COUNT + k] = red[0];
-        __syncthreads();
-    }
-}
-
-__global__ void diag_final_kernel(const double* __restrict__ partials, int nparts,
-                                  double* __restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= DIAG_COUNT) return;
-    const bool is_max = (k == DIAG_MAX_PHI || k == DIAG_MAX_PSI || k == DIAG_MAX_LAP);
-    double a = 0.0;
-    for (int b = 0; b < nparts; ++b) {
-        const double v = partials[(long long)b * DIAG_COUNT + k];
-        a = is_max ? fmax(a, v) : a + v;
-    }
-    out[k] = a;
-}
-
 // ---- bandwidth probe: R streamed reads and W streamed writes of 16-byte
 // elements, grid-stride, no reuse (the measured HBM ceiling for kernels shaped
 // like the stage kernels; also the plain copy used to calibrate byte counters)
@@ -1153,24 +1074,6 @@ int launch_probe(int kind, void* const* in, void* const* out, long long n16, int
         case 2: hipLaunchKernelGGL((probe_kernel<5, 2>), dim3(blocks), dim3(256), 0, s, a[0], a[1], a[2], a[3], a[4], o0, o1, n16); break;
         default: return (int)hipErrorInvalidValue;
     }
-    return (int)hipGetLastError();
-}
-
-int diag_partials_needed(int nx, int ny, int nz) {
-    const long long rows = (long long)ny * nz;
-    return (int)(rows < 4096 ? rows : 4096);
-}
-
-int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, double* partials,
-                       int nparts, double* out, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
-    if (prec == PREC_F32C)
-        hipLaunchKernelGGL((diag_kernel<true>), dim3(nparts), dim3(DIAG_THREADS), 0, s, desc, parity,
-                           c, partials);
-    else
-        hipLaunchKernelGGL((diag_kernel<false>), dim3(nparts), dim3(DIAG_THREADS), 0, s, desc, parity,
-                           c, partials);
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, nparts, out);
     return (int)hipGetLastError();
 }
 

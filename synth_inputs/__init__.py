@@ -236,3 +236,30 @@ def serving_trace(count: int = 300, rate: float = 50.0, seed: int = 12345,
                      phi1=_zeros(nn), meta={"seed": 10000 + j})
         out.append(ServeRequest(j, t, w, prec))
     return out
+
+
+def radial_sweep(count: int = 4096, m: int = 1000, dr: float = 5e-4, R: float = 0.3,
+                 seed: int = 7):
+    """A parameter sweep of radial solves (the section 2.2 form of Example 3):
+    phi0 = A b(r), phi1 = a A b(r) with b the paper's bump of radius R on the
+    nodes r_i = i dr; per solve A ~ U[0.5, 2], a ~ U[-8, 0], mu2 ~ U[1, 9],
+    lambda ~ U[0.5, 4], drawn in that order from ``default_rng(seed)``.
+    Returns (phi0, phi1, params): the solves back to back (count * m values
+    each) and a list of (mu2, lambda) pairs."""
+    rng = np.random.default_rng(seed)
+    r = np.arange(m) * dr
+    b = np.zeros(m)
+    inside = r < R
+    b[inside] = np.exp(1.0 / (R * R) - 1.0 / (R * R - r[inside] ** 2))
+    phi0 = np.empty(count * m)
+    phi1 = np.empty(count * m)
+    params = []
+    for i in range(count):
+        A = rng.uniform(0.5, 2.0)
+        a = rng.uniform(-8.0, 0.0)
+        mu2 = rng.uniform(1.0, 9.0)
+        lam = rng.uniform(0.5, 4.0)
+        phi0[i * m:(i + 1) * m] = A * b
+        phi1[i * m:(i + 1) * m] = a * A * b
+        params.append((mu2, lam))
+    return phi0, phi1, params

@@ -177,3 +177,26 @@ def test_radial_errors(hb):
     with pytest.raises(hb.HBError) as e:
         hb.hb_radial_solve([bad], x, x.copy())
     assert e.value.code == hb.HB_E_CFL
+
+
+def test_radial_sweep_full_size_sampled(hb):
+    """The benchmark's radial sweep (4096 solves x 1000 nodes x 2000 steps, one
+    launch, device-resident state): three solves against the oracle, each
+    within max(1e-12, 20 x its noise floor)."""
+    import torch
+    import synth_inputs as si
+    count, m, steps, dr, dt, invL2 = 4096, 1000, 2000, 5e-4, 1e-4, 1 / 25
+    phi0, phi1, params = si.radial_sweep(count, m, dr)
+    cfgs = [hb.make_radial_config(m, dr, mu2, lam, dt, steps, 0.0, invL2) for mu2, lam in params]
+    phi = torch.from_numpy(phi0).cuda()
+    psi = torch.from_numpy(phi1).cuda()
+    hb.hb_radial_solve(cfgs, phi, psi)
+    phi, psi = phi.cpu().numpy(), psi.cpu().numpy()
+    for i in (0, 1, count - 1):
+        mu2, lam = params[i]
+        p0, p1 = phi0[i * m:(i + 1) * m], phi1[i * m:(i + 1) * m]
+        ref = radial_solve(p0, p1, dr, mu2, lam, dt, steps, t0=0.0, inv_L2=invL2)
+        tol, floor = bar(p0, p1, ref, dr, mu2, lam, dt, steps, 0.0, invL2)
+        err = rel(phi[i * m:(i + 1) * m], psi[i * m:(i + 1) * m], *ref)
+        print(f"sweep solve {i} (mu2 {mu2:.2f}, lambda {lam:.2f}): err {err:.3e}, floor {floor:.3e}")
+        assert err <= tol
