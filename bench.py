@@ -165,10 +165,10 @@ def run_serve(count, rate, budget_gb):
             "span_s": res["span_s"]}
 
 
-# radial batch kernel: LDS bytes per node-step (reads + writes of its LDS
-# arrays over the four stages: 39 reads and 9 writes of 8 B) and the LDS
-# peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
-RADIAL_LDS_BYTES = 48 * 8
+# radial batch kernel: LDS bytes per node-step (per stage one write of the
+# stage input and five stencil reads, 8 B each; the state stays in registers)
+# and the LDS peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
+RADIAL_LDS_BYTES = 4 * 6 * 8
 LDS_PEAK_GBS = 128 * 256 * 2.4
 
 

@@ -8,10 +8,14 @@
 //           u[-1] = u[1], u[-2] = u[2] (the symmetric ghost of section 2.2),
 //   zeros at and beyond r = R; classical RK4 in time.
 //
-// One workgroup per solve; the whole state lives in LDS and the workgroup runs
-// all of its time steps in one launch (solves are independent, so no grid
-// synchronisation is needed).  Stage inputs are formed as in the 3-D kernels
-// (G storage: only the psi component of each stage derivative is kept).
+// One workgroup per solve; the workgroup runs all of its time steps in one
+// launch (solves are independent, so no grid synchronisation is needed).
+// Thread t owns nodes t, t + 256, ...: their Y_phi, Y_psi and G1..G3 stay in
+// registers.  Only the stage input S_phi, whose stencil spans other threads'
+// nodes, goes through LDS, in two buffers used by alternate stages, so each
+// stage needs one barrier.  The owners of nodes 1 and 2 also write the even
+// ghosts S[-1], S[-2].  Stage inputs are formed as in the 3-D kernels (G
+// storage: only the psi component of each stage derivative is kept).
 #include <hip/hip_runtime.h>
 
 #include "hb_internal.h"
@@ -24,46 +28,63 @@ constexpr int RAD_THREADS = 256;
 template <typename T>
 using gptr = __attribute__((address_space(1))) T*;
 
+template <int NPT>
 __global__ void __launch_bounds__(RAD_THREADS)
 radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
               double* __restrict__ psi) {
     extern __shared__ double lds[];
     const RadialDesc d = descs[blockIdx.x];
     const int m = d.m;
-    // LDS: S (stage input, with 2 leading ghost slots and 2 trailing zeros),
-    // Y_phi, Y_psi, G1, G2, G3
-    double* S = lds + 2;              // S[-2 .. m+1]
-    double* Yp = lds + (m + 4);
-    double* Ys = Yp + m;
-    double* G1 = Ys + m;
-    double* G2 = G1 + m;
-    double* G3 = G2 + m;
+    // two stage-input buffers, each S[-2 .. m+1]: 2 ghost slots, the nodes,
+    // and 2 zeros at and beyond r = R
+    double* const Sb[2] = {lds + 2, lds + (m + 4) + 2};
+    if (threadIdx.x < 8) {
+        const int b = threadIdx.x >> 2, k = threadIdx.x & 3;
+        Sb[b][k < 2 ? k - 2 : m + k - 2] = 0.0;
+    }
     gptr<double> gp = (gptr<double>)(phi + d.offset);
     gptr<double> gs = (gptr<double>)(psi + d.offset);
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        Yp[i] = gp[i];
-        Ys[i] = gs[i];
+    double yp[NPT], ys[NPT], g1[NPT], g2[NPT], g3[NPT], sv[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int i = threadIdx.x + k * RAD_THREADS;
+        yp[k] = i < m ? gp[i] : 0.0;
+        ys[k] = i < m ? gs[i] : 0.0;
+        g1[k] = g2[k] = g3[k] = sv[k] = 0.0;
     }
-    if (threadIdx.x < 2) S[m + threadIdx.x] = 0.0;  // phi(R) = 0 and beyond
-    __syncthreads();
 
     const double dr = d.dr, mu2 = d.mu2, lam = d.lambda, dt = d.dt;
     const double hdt = dt / 2.0, dt6 = dt / 6.0;
     const double idr2 = 1.0 / (dr * dr), i12dr = 1.0 / (12.0 * dr);
 
-    // radial operator at node i from S (ghosts filled)
-    auto op = [&](int i) {
+    // 2/r at the owned nodes, divided once (kept in registers up to 8 nodes
+    // per thread; recomputed, with the same result, beyond)
+    constexpr bool KEEP_2R = NPT <= 8;
+    double two_r[KEEP_2R ? NPT : 1];
+#pragma unroll
+    for (int k = 0; k < (KEEP_2R ? NPT : 1); ++k) {
+        const int i = threadIdx.x + k * RAD_THREADS;
+        two_r[k] = i > 0 ? 2.0 / ((double)i * dr) : 0.0;
+    }
+    // radial operator at node i (the thread's k-th) from S (ghosts filled)
+    auto op = [&](const double* S, int i, int k) {
         const double um2 = S[i - 2], um1 = S[i - 1], u0 = S[i], up1 = S[i + 1], up2 = S[i + 2];
         const double urr = (-1.0 / 12.0 * um2 + 4.0 / 3.0 * um1 - 5.0 / 2.0 * u0 + 4.0 / 3.0 * up1
                             - 1.0 / 12.0 * up2) * idr2;
         if (i == 0) return 3.0 * urr;
         const double ur = (um2 - 8.0 * um1 + 8.0 * up1 - up2) * i12dr;
-        return 2.0 / ((double)i * dr) * ur + urr;
+        const double tr = KEEP_2R ? two_r[KEEP_2R ? k : 0] : 2.0 / ((double)i * dr);
+        return tr * ur + urr;
     };
-    auto ghosts = [&]() {
-        if (threadIdx.x == 0) {
-            S[-1] = m > 1 ? S[1] : 0.0;
-            S[-2] = m > 2 ? S[2] : 0.0;
+    // publish this thread's stage inputs sv into S (and the mirrored ghosts)
+    auto put = [&](double* S) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = threadIdx.x + k * RAD_THREADS;
+            if (i < m) {
+                S[i] = sv[k];
+                if (i == 1 || i == 2) S[-i] = sv[k];
+            }
         }
     };
 
@@ -73,73 +94,106 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
         const double c2 = exp(-2.0 * (t + dt / 2.0)) * d.inv_L2;
         const double c4 = exp(-2.0 * (t + dt)) * d.inv_L2;
         // stage 1: S = Y_phi, S_psi = Y_psi
-        for (int i = threadIdx.x; i < m; i += blockDim.x) S[i] = Yp[i];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) sv[k] = yp[k];
+        put(Sb[0]);
         __syncthreads();
-        ghosts();
-        __syncthreads();
-        for (int i = threadIdx.x; i < m; i += blockDim.x) {
-            const double s = S[i];
-            G1[i] = -3.0 * Ys[i] + c1 * op(i) + mu2 * s - lam * s * s * s;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = threadIdx.x + k * RAD_THREADS;
+            if (i < m) {
+                const double s = sv[k];
+                g1[k] = -3.0 * ys[k] + c1 * op(Sb[0], i, k) + mu2 * s - lam * s * s * s;
+            }
         }
-        __syncthreads();
         // stage 2: S = Y_phi + dt/2 Y_psi, S_psi = Y_psi + dt/2 G1
-        for (int i = threadIdx.x; i < m; i += blockDim.x) S[i] = Yp[i] + hdt * Ys[i];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) sv[k] = yp[k] + hdt * ys[k];
+        put(Sb[1]);
         __syncthreads();
-        ghosts();
-        __syncthreads();
-        for (int i = threadIdx.x; i < m; i += blockDim.x) {
-            const double s = S[i];
-            G2[i] = -3.0 * (Ys[i] + hdt * G1[i]) + c2 * op(i) + mu2 * s - lam * s * s * s;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = threadIdx.x + k * RAD_THREADS;
+            if (i < m) {
+                const double s = sv[k];
+                g2[k] = -3.0 * (ys[k] + hdt * g1[k]) + c2 * op(Sb[1], i, k) + mu2 * s - lam * s * s * s;
+            }
         }
-        __syncthreads();
         // stage 3: S = Y_phi + dt/2 (Y_psi + dt/2 G1), S_psi = Y_psi + dt/2 G2
-        for (int i = threadIdx.x; i < m; i += blockDim.x) S[i] = Yp[i] + hdt * (Ys[i] + hdt * G1[i]);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) sv[k] = yp[k] + hdt * (ys[k] + hdt * g1[k]);
+        put(Sb[0]);
         __syncthreads();
-        ghosts();
-        __syncthreads();
-        for (int i = threadIdx.x; i < m; i += blockDim.x) {
-            const double s = S[i];
-            G3[i] = -3.0 * (Ys[i] + hdt * G2[i]) + c2 * op(i) + mu2 * s - lam * s * s * s;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = threadIdx.x + k * RAD_THREADS;
+            if (i < m) {
+                const double s = sv[k];
+                g3[k] = -3.0 * (ys[k] + hdt * g2[k]) + c2 * op(Sb[0], i, k) + mu2 * s - lam * s * s * s;
+            }
         }
-        __syncthreads();
         // stage 4: S = Y_phi + dt (Y_psi + dt/2 G2), S_psi = Y_psi + dt G3; update
-        for (int i = threadIdx.x; i < m; i += blockDim.x) S[i] = Yp[i] + dt * (Ys[i] + hdt * G2[i]);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) sv[k] = yp[k] + dt * (ys[k] + hdt * g2[k]);
+        put(Sb[1]);
         __syncthreads();
-        ghosts();
-        __syncthreads();
-        for (int i = threadIdx.x; i < m; i += blockDim.x) {
-            const double s = S[i];
-            const double ys = Ys[i], e1 = G1[i], e2 = G2[i], e3 = G3[i];
-            const double spsi4 = ys + dt * e3;
-            const double g4 = -3.0 * spsi4 + c4 * op(i) + mu2 * s - lam * s * s * s;
-            const double k2 = ys + hdt * e1, k3 = ys + hdt * e2;
-            Yp[i] = Yp[i] + dt6 * (ys + 2.0 * k2 + 2.0 * k3 + spsi4);
-            Ys[i] = ys + dt6 * (e1 + 2.0 * e2 + 2.0 * e3 + g4);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int i = threadIdx.x + k * RAD_THREADS;
+            if (i < m) {
+                const double s = sv[k];
+                const double y2 = ys[k], e1 = g1[k], e2 = g2[k], e3 = g3[k];
+                const double spsi4 = y2 + dt * e3;
+                const double g4 = -3.0 * spsi4 + c4 * op(Sb[1], i, k) + mu2 * s - lam * s * s * s;
+                const double k2 = y2 + hdt * e1, k3 = y2 + hdt * e2;
+                yp[k] = yp[k] + dt6 * (y2 + 2.0 * k2 + 2.0 * k3 + spsi4);
+                ys[k] = y2 + dt6 * (e1 + 2.0 * e2 + 2.0 * e3 + g4);
+            }
         }
-        __syncthreads();
+        // (the next stage 1 writes Sb[0], last read in stage 3, before this
+        // stage's barrier)
     }
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        gp[i] = Yp[i];
-        gs[i] = Ys[i];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int i = threadIdx.x + k * RAD_THREADS;
+        if (i < m) {
+            gp[i] = yp[k];
+            gs[i] = ys[k];
+        }
     }
+}
+
+template <int NPT>
+hipError_t launch_radial_t(const RadialDesc* descs, int count, size_t bytes, double* phi,
+                           double* psi, hipStream_t s) {
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)radial_kernel<NPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((radial_kernel<NPT>), dim3(count), dim3(RAD_THREADS), bytes, s, descs, phi,
+                       psi);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-size_t radial_lds_bytes(int max_m) { return (size_t)(6 * max_m + 4) * sizeof(double); }
+size_t radial_lds_bytes(int max_m) { return (size_t)(2 * (max_m + 4)) * sizeof(double); }
 
 int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
                   void* stream) {
     if (count <= 0) return 0;
     const size_t bytes = radial_lds_bytes(max_m);
-    if (bytes > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)radial_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return (int)e;
-    }
-    hipLaunchKernelGGL(radial_kernel, dim3(count), dim3(RAD_THREADS), radial_lds_bytes(max_m),
-                       (hipStream_t)stream, descs, phi, psi);
-    return (int)hipGetLastError();
+    hipStream_t s = (hipStream_t)stream;
+    const int npt = (max_m + RAD_THREADS - 1) / RAD_THREADS;
+    hipError_t e;
+    if (npt <= 1) e = launch_radial_t<1>(descs, count, bytes, phi, psi, s);
+    else if (npt <= 2) e = launch_radial_t<2>(descs, count, bytes, phi, psi, s);
+    else if (npt <= 4) e = launch_radial_t<4>(descs, count, bytes, phi, psi, s);
+    else if (npt <= 8) e = launch_radial_t<8>(descs, count, bytes, phi, psi, s);
+    else if (npt <= 11) e = launch_radial_t<11>(descs, count, bytes, phi, psi, s);
+    else return (int)hipErrorInvalidValue;
+    return (int)e;
 }
 
 }  // namespace hb
