@@ -37,6 +37,10 @@ CASES = [
     (5, 0.2, 2.0, 1.0, 1.0, 0.0, 0.01, 40, 1.0, 0.5, 0.7),
     (1, 0.5, 2.0, 1.0, 1.0, 0.0, 0.01, 40, 1.0, 0.5, 0.7),
     (2700, 2e-4, 9.0, 2.0, 1 / 25, 0.0, 5e-5, 200, 1.0, -5.0, 0.3),
+    # every nodes-per-thread variant of the kernel (256 threads): 1, 2, 4, 8, 11
+    (300, 1e-3, 4.0, 1.5, 1 / 25, 0.0, 1e-4, 300, 1.0, -3.0, 0.25),
+    (1500, 3e-4, 2.0, 0.5, 1 / 25, 0.1, 1e-4, 150, 1.5, -2.0, 0.35),
+    (257, 2e-3, 1.0, 1.0, 1 / 25, 0.0, 2e-4, 200, 1.0, 1.0, 0.4),
 ]
 
 
