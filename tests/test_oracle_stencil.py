@@ -16,7 +16,6 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-import oracle
 from oracle.radial import radial_operator
 
 
