@@ -1,13 +1,13 @@
-// HIP kernels for gfx950: one RK4 stage of the Higgs boson equation in de
-// Sitter spacetime per launch (Balogh, Banda, Yagdjian, section 2.1).
+// HIP kernels for gfx950: the RK4 steps of the Higgs boson equation in de
+// Sitter spacetime (Balogh, Banda, Yagdjian, section 2.1) on a 3-D grid.
 //
 // System (eq. (rhs)):  phi_t = psi,
 //                      psi_t = -3 psi + c(t) Lap_h phi + mu2 phi - lambda phi^3,
 // with the fourth-order 13-point Laplacian of section 2.1 and classical RK4.
 //
-// Storage scheme ("G storage", 19 field passes per step).  Only the psi
-// component of each stage derivative needs storing, because the phi component
-// of k_s is the psi component of the stage-s input:
+// Storage scheme ("G storage").  Only the psi component of each stage
+// derivative needs storing, because the phi component of k_s is the psi
+// component of the stage-s input:
 //   G_s = g(t_s, S_phi,s, S_psi,s),  g(phi, psi) = -3 psi + c Lap phi + mu2 phi - lambda phi^3
 //   S_phi,1 = Y_phi                          S_psi,1 = Y_psi
 //   S_phi,2 = Y_phi + dt/2 Y_psi             S_psi,2 = Y_psi + dt/2 G1
@@ -15,23 +15,21 @@
 //   S_phi,4 = Y_phi + dt   S_psi,3           S_psi,4 = Y_psi + dt   G3
 //   phi' = Y_phi + dt/6 (Y_psi + 2 S_psi,2 + 2 S_psi,3 + S_psi,4)
 //   psi' = Y_psi + dt/6 (G1 + 2 G2 + 2 G3 + G4)
-// which is the classical RK4 update with each stage input formed in the same
-// order as the textbook form.  Stage s reads, per point,
-//   s=1: Y_phi (stencil), Y_psi                        -> writes G1
-//   s=2: Y_phi, Y_psi (stencil), G1                     -> writes G2
-//   s=3: Y_phi, Y_psi, G1 (stencil), G2                 -> writes G3
-//   s=4: Y_phi, Y_psi, G2 (stencil), G1, G3             -> writes Y'_phi, Y'_psi
-// The state ping-pongs by step parity (stage 4 stencil-reads Y while writing Y').
+// which is the classical RK4 update.  One pass per stage would read, per point,
+//   s=1: Y_phi (stencil), Y_psi                        -> write G1
+//   s=2: Y_phi, Y_psi (stencil), G1                     -> write G2
+//   s=3: Y_phi, Y_psi, G1 (stencil), G2                 -> write G3
+//   s=4: Y_phi, Y_psi, G2 (stencil), G1, G3             -> write Y'_phi, Y'_psi
+// (19 field passes).  The state ping-pongs by step parity.
 //
-// Kernel shape.  A block owns a 64 x BY column tile (64-wide = one wavefront
-// per row) and marches a z-range.  Each thread keeps its own column's stage
-// input S_phi at planes z-2..z+2 in registers (the z part of the star), and
-// the block stages plane z with a 2-cell x/y halo in LDS (the x and y parts).
-// The raw fields of the thread's own column are loaded three planes ahead and
-// those of the halo one plane ahead, so each plane's loads are in flight while
-// the previous plane computes.  One __syncthreads per plane (double-buffered
-// LDS).  No MFMA: the stencil is not a contraction and the path is bound by
-// HBM bandwidth.
+// Three schemes, bitwise equal (they share the per-point arithmetic below):
+//   stage_kernel  one launch per stage (19 passes per step);
+//   pair_kernel   stages 1+2 and 3+4 per launch (10 passes);
+//   step_kernel   the whole step per launch (4 passes: Y in, Y' out), the
+//                 default.
+// All march z with a register queue per column (the z part of the stencil)
+// and stage each x-y plane with its halo in LDS (the x and y parts).  No
+// MFMA: the stencil is not a contraction.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
