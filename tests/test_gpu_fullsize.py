@@ -69,6 +69,18 @@ def test_cube256_2000_steps_vs_oracle_samples(hb):
     assert abs(d["integral"] - g["integral"]) <= 1e-11 * scale
 
 
+def test_cube256_2000_steps_fp32c_vs_oracle_samples(hb):
+    """The FP32c form of the benchmark workload (its FP32-storage default
+    tiling) against the FP64 oracle samples: within 1e-5 relative."""
+    g = load_gold("cube256_gauss8_oracle.json")
+    w = si.config2()
+    phi, psi, d = gpu_run(hb, w, g["steps"], precision=1)
+    err = sampled_error(g, phi, psi)
+    print(f"256^3 x {g['steps']} FP32c: sampled relative max-norm error {err:.3e}")
+    assert err <= 1e-5
+    assert d["nonfinite"] == 0
+
+
 def test_cube256_10_steps_every_node(hb, oracle_mod):
     w = si.config2()
     phi, psi, _ = gpu_run(hb, w, 10)
