@@ -2,7 +2,8 @@
 
 Bar: FP64 state-vector relative max norm <= 1e-12 (elementwise comparison);
 FP32c (FP32 storage/stencil, compensated state) <= 1e-5 against the FP64
-oracle.  Sizes span several 64 x BY tiles, ragged x/y/z tails and z-chunks.
+oracle.  Sizes span several tiles of every scheme's shapes, ragged x/y/z
+tails and z-chunks.
 """
 import numpy as np
 import pytest
@@ -249,3 +250,46 @@ def test_nonfinite_detected(hb):
         assert hb.hb_diagnostics(h, allow_nonfinite=True)["nonfinite"] > 1
     finally:
         hb.hb_destroy(h)
+
+
+def random_cases(count=16, seed=2024):
+    """Seeded random configurations: shape, box aspect (anisotropic h),
+    coefficients (lambda of both signs), start time, c(t) scale, dt inside the
+    stability limit, steps, precision, scheme and tiling."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for k in range(count):
+        n = tuple(int(v) for v in rng.integers(1, 90, size=3))
+        L = float(rng.uniform(4.0, 20.0))
+        mu2 = float(rng.uniform(0.0, 9.0))
+        lam = float(rng.choice([-1.0, 1.0]) * rng.uniform(0.1, 4.0))
+        t0 = float(rng.uniform(0.0, 1.0))
+        inv_L2 = float(rng.uniform(0.05, 1.0))
+        steps = int(rng.integers(1, 14))
+        prec = int(rng.integers(0, 2))
+        flags = [0, 0, 8, 4][int(rng.integers(0, 4))]          # whole-step (x2), pairs, stages
+        tiling = (int(rng.choice([8, 16])), int(rng.choice([0, 1, 3, 7, 32])))
+        cases.append((k, n, L, mu2, lam, t0, inv_L2, steps, prec, flags, tiling))
+    return cases
+
+
+def random_dt(w, inv_L2, t0):
+    """dt at 40% of the RK4 stability limit of the stencil part (section 2.1
+    symbol), and at most 0.02 so that the few steps stay far from the
+    finite-time blow-up of the focusing (lambda < 0) cases."""
+    rho = sum(16.0 / (3.0 * hd * hd) for hd in w.h)
+    return min(0.02, 0.4 * 2.0 * np.sqrt(2.0) / np.sqrt(inv_L2 * np.exp(-2.0 * t0) * rho))
+
+
+@pytest.mark.parametrize("case", random_cases(), ids=lambda c: f"r{c[0]}_{c[1][0]}x{c[1][1]}x{c[1][2]}")
+def test_random_configurations(hb, oracle_mod, case):
+    k, n, L, mu2, lam, t0, inv_L2, steps, prec, flags, tiling = case
+    w = si.small_case(*n, seed=100 + k, steps=steps, L=L, mu2=mu2, lam=lam, t0=t0,
+                      inv_L2=inv_L2)
+    w.dt = random_dt(w, inv_L2, t0)
+    g = run_gpu(hb, w, precision=prec, flags=flags, tiling=tiling)
+    r = oracle.solve_workload(w)
+    assert np.all(np.isfinite(r[0])) and np.all(np.isfinite(r[1]))
+    err = oracle.rel_maxnorm(*g, *r)
+    print(f"case {case}: rel err {err:.3e}")
+    assert err <= (TOL32C if prec else TOL64)
