@@ -165,6 +165,22 @@ def run_serve(count, rate, budget_gb):
             "span_s": res["span_s"]}
 
 
+def run_shard(steps, warmup):
+    """One GPU's share of the 512^3 workload under an 8-way z-slab split:
+    512 x 512 x 64 (FP64), timed like the main leg; the slab's own zero halo
+    stands in for the planes a neighbour would send."""
+    import synth_inputs as si
+    w = si.config3()
+    n, lo, hi = (512, 512, 64), (w.lo[0], w.lo[1], -4.0), (w.hi[0], w.hi[1], 4.0)  # middle slab
+    sw = si.Workload("slab512x512x64", n, lo, hi, mu2=w.mu2, lam=w.lam, dt=w.dt, steps=steps,
+                     phi0=lambda: si.cinf_bump(n, lo, hi, 0.8, 10.0), phi1=si._zeros(n))
+    elapsed, stage_ms, _ = run_gpu(sw, 0, steps, warmup, 20)
+    return {"grid": [512, 512, 64], "steps": steps,
+            "pt_updates_per_s": sw.points * steps / elapsed,
+            "ms_per_step": elapsed / steps * 1e3, "kernel_ms": sum(stage_ms),
+            "own_GBps": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9}
+
+
 # radial batch kernel: LDS bytes per node-step (per stage one write of the
 # stage input and five stencil reads, 8 B each; the state stays in registers)
 # and the LDS peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
@@ -247,6 +263,7 @@ def main():
     ap.add_argument("--serve-sweep-count", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-radial", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
                     help="3-D scheme of the single-solve legs: the whole-step kernel (default) "
                          "or, for comparison, the stage-pair or per-stage kernels")
@@ -334,6 +351,8 @@ def main():
             print(f"serve sweep: {rate} req/s: p50 {r['p50_latency_s']:.3f} s, "
                   f"p99 {r['p99_latency_s']:.3f} s, {r['solves_per_s']:.2f} solves/s",
                   file=sys.stderr, flush=True)
+    if not args.no_shard:
+        out["shard"] = run_shard(200, 10)
     if not args.no_radial:
         out["radial"] = run_radial(args.radial_count, 1000, args.radial_steps,
                                    0 if args.no_cpu else 4)
