@@ -20,9 +20,9 @@ Prints ONE JSON line.  Extra objects:
                    --forms is given;
   hbm_probe     -- with --probe, the streamed-bandwidth ceiling measured by
                    the library's copy and 5-read/2-write probe kernels;
-  batched       -- 64 uneven solves (N ~ U{64..192}^3, 500 steps) in one launch
-                   per stage pair, FP64 and FP32c, vs the same solves run one
-                   by one;
+  batched       -- 64 uneven solves (N ~ U{64..192}^3, 500 steps), one
+                   whole-step launch per step and precision over all of them,
+                   FP64 and FP32c, vs the same solves run one by one;
   served        -- a Poisson request stream (50/s, N in {48..384}^3, 200-2000
                    steps, FP64/FP32c) through the continuous-batching pool:
                    p50/p99 latency and solves/s (offered load is far above
@@ -95,8 +95,8 @@ def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0):
 
 
 def run_batch(count, steps, warmup):
-    """64 uneven solves (N ~ U{64..192}^3) advanced together: one launch per
-    stage pair per precision over a tile table spanning all solves, hipGraph
+    """64 uneven solves (N ~ U{64..192}^3) advanced together: one whole-step
+    launch per step and precision over a tile table spanning all solves, hipGraph
     replay of 16-step chunks.  Baseline: the same solves one after another
     through the single-solve path (also graph-replayed), same GPU."""
     import torch

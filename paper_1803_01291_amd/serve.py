@@ -2,7 +2,7 @@
 
 Requests (a configuration, initial data, a step count, an arrival time) are
 admitted into the device-resident pool as slots and HBM budget free up; every
-admitted solve advances in the same stage-pair launches as the others, new
+admitted solve advances in the same whole-step launches as the others, new
 ones join at step boundaries while others are mid-flight, and finished ones
 are read back and released.  The loop itself is host orchestration: all
 arithmetic runs in libhb's kernels.

@@ -1,5 +1,5 @@
 """Full-size parity in the launch configuration bench.py times (library
-default tiling, stage-pair kernels).
+default tiling, whole-step kernel).
 
 * 256^3 x 2000 steps (the benchmark workload): GPU vs oracle reference values
   stored by tests/golden/make_golden.py (an oracle-only script) at sampled
