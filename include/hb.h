@@ -79,7 +79,8 @@ typedef struct hb_config {
     double t0;           /* initial time                                            */
     double dt;           /* RK4 time step (> 0)                                     */
     int32_t precision;   /* HB_F64 or HB_F32C                                       */
-    uint32_t flags;      /* HB_ALLOW_UNSTABLE | HB_USE_GRAPH                        */
+    uint32_t flags;      /* HB_ALLOW_UNSTABLE | HB_USE_GRAPH | HB_PAIRWISE |        */
+                         /* HB_STAGEWISE                                            */
     void* stream;        /* hipStream_t to order work on, or NULL                   */
 } hb_config;
 
@@ -168,18 +169,22 @@ int hb_autotune(hb_solver* s, int trial_steps, int* by, int* zc);
 /* Free everything (NULL-safe). */
 int hb_destroy(hb_solver* s);
 
-/* Device bytes hb_create would allocate for cfg (0 on invalid cfg). */
+/* Device bytes hb_create would allocate for cfg (0 on invalid cfg): per
+ * field, the padded grid; the whole-step scheme allocates Y_phi and Y_psi
+ * twice (step parity) plus, for HB_F32C, the two FP32 low parts (32 B or 24 B
+ * per padded cell); HB_PAIRWISE and HB_STAGEWISE add the G1..G3 fields. */
 size_t hb_footprint(const hb_config* cfg);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* hb_last_error(void);
 
-/* ---- batched form: many independent solves, one launch per RK4 stage ------ */
+/* ---- batched form: many independent solves in shared launches -------------- */
 
 /* count solves with their own grid, coefficients, dt and precision.  All
- * solves of one precision advance together in one launch per stage over a
- * device tile table spanning them.  Results are bitwise equal to hb_step on
- * the same solve.  stream: hipStream_t or NULL. */
+ * solves of one precision advance together, one launch per kernel of the
+ * scheme (one per step by default) over a device tile table spanning them.
+ * Every config must select the same scheme (HB_E_ARG otherwise).  Results are
+ * bitwise equal to hb_step on the same solve.  stream: hipStream_t or NULL. */
 int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** out);
 int hb_batch_set_initial(hb_batch* b, int i, const void* phi0, const void* phi1, int mem, int dtype);
 int hb_batch_step(hb_batch* b, int64_t nsteps);
@@ -194,14 +199,16 @@ int hb_batch_destroy(hb_batch* b);
 int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out);
 
 /* Admit one solve of `steps` steps with initial data (as hb_set_initial).
- * Returns HB_E_BUSY (nothing allocated, nothing changed) when no slot is free
- * or hb_footprint(cfg) exceeds the unused budget.  The solve joins the active
- * set at the next hb_pool_advance. */
+ * Pool solves run the whole-step kernel: a cfg with HB_PAIRWISE or
+ * HB_STAGEWISE is rejected (HB_E_ARG).  Returns HB_E_BUSY (nothing allocated,
+ * nothing changed) when no slot is free or the solve's device bytes (those of
+ * hb_footprint(cfg), with a coefficient table for `steps`) exceed the unused
+ * budget.  The solve joins the active set at the next hb_pool_advance. */
 int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void* phi1, int mem,
                   int dtype, int64_t steps, int* slot);
 
 /* Advance every active solve by up to k steps (each stops at its own step
- * count); one launch per stage per precision over all of them. */
+ * count); one whole-step launch per step and precision over all of them. */
 int hb_pool_advance(hb_pool* p, int k);
 
 /* Slots that finished since the last poll (up to cap); *ndone is the count. */

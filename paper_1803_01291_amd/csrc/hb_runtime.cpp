@@ -1,5 +1,5 @@
 // Host runtime of libhb: layout planning, device allocation, coefficient
-// tables, launch groups (one or many solves per stage launch), hipGraph step
+// tables, launch groups (one or many solves per launch), hipGraph step
 // replay, the autotuner and the C ABI declared in include/hb.h.
 #include <hip/hip_runtime.h>
 
@@ -57,16 +57,36 @@ long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
 // ---- layout ------------------------------------------------------------------
 
+// Schemes (one launch per RK4 step, per stage pair or per stage; bitwise-equal
+// results).  The whole-step kernel keeps G1..G3 on chip, so its solves do not
+// allocate them.
+enum Scheme { SCHEME_STEP = 0, SCHEME_PAIRS = 1, SCHEME_STAGES = 2 };
+
+int scheme_of(uint32_t flags) {
+    if (flags & HB_STAGEWISE) return SCHEME_STAGES;
+    if (flags & HB_PAIRWISE) return SCHEME_PAIRS;
+    return SCHEME_STEP;
+}
+
+// Device fields of a solve, by index: 0, 1 Y_phi (ping-pong by step parity),
+// 2, 3 Y_psi, 4..6 G1..G3 (stage-pair and per-stage schemes), 7, 8 the FP32
+// low parts of phi and psi (FP32c).
+bool field_used(int k, int precision, int scheme) {
+    if (k >= 4 && k <= 6) return scheme != SCHEME_STEP;
+    if (k >= 7) return precision == HB_F32C;
+    return true;
+}
+
 struct Layout {
     int nx, ny, nz;
     size_t esz;             // bytes per element
     long long sy, sz;       // row / plane pitch (elements)
     long long origin_off;   // elements from field start to interior (0,0,0)
     long long field_elems;  // elements per field (multiple of 256 bytes)
-    int nfields;            // 7 (FP64) or 9 (FP32c: + lo_phi, lo_psi)
+    int nfields;            // fields allocated (field_used): 4 or 6 whole-step, 7 or 9 otherwise
 };
 
-Layout plan_layout(const hb_config& c) {
+Layout plan_layout(const hb_config& c, int scheme) {
     Layout L;
     L.nx = c.n[0];
     L.ny = c.n[1];
@@ -82,7 +102,8 @@ Layout plan_layout(const hb_config& c) {
     const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
                            L.nx + 2;
     L.field_elems = round_up(last, 256 / (long long)L.esz);
-    L.nfields = c.precision == HB_F32C ? 9 : 7;
+    L.nfields = 0;
+    for (int k = 0; k < 9; ++k) L.nfields += field_used(k, c.precision, scheme) ? 1 : 0;
     return L;
 }
 
@@ -104,7 +125,7 @@ int validate(const hb_config* c) {
     if (c->precision != HB_F64 && c->precision != HB_F32C) return fail(HB_E_ARG, "bad precision");
     {
         // the whole-step kernel addresses a plane with 32-bit byte offsets
-        const Layout L = plan_layout(*c);
+        const Layout L = plan_layout(*c, SCHEME_STEP);
         if ((double)L.sz * L.esz >= 2147483648.0)
             return fail(HB_E_ARG, "an x-y plane (%lld x %lld padded cells) must be under 2 GiB",
                         L.sy, (long long)c->n[1] + 4);
@@ -132,6 +153,7 @@ struct Solve {
     Layout L{};
     char* mem = nullptr;          // all fields, one allocation
     void* f[9] = {};              // origins: phi0, phi1, psi0, psi1, G1, G2, G3, lo_phi, lo_psi
+                                  // (NULL where not allocated)
     double* ctab = nullptr;       // device c(t) table, 4 per step
     long long ctab_steps = 0;
     long long nstep = 0;          // host mirror of the device counter
@@ -154,15 +176,15 @@ long long ctab_capacity(long long need, long long have) {
 }
 
 // device bytes of one solve whose coefficient table covers `steps` steps
-size_t solve_footprint(const hb_config& c, long long steps) {
-    const Layout L = plan_layout(c);
+size_t solve_footprint(const hb_config& c, int scheme, long long steps) {
+    const Layout L = plan_layout(c, scheme);
     return field_bytes(L) * (size_t)L.nfields +
            (size_t)ctab_capacity(steps, 0) * 4 * sizeof(double);
 }
 
-int solve_alloc(Solve& s, const hb_config& c, hipStream_t stream) {
+int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
     s.cfg = c;
-    s.L = plan_layout(c);
+    s.L = plan_layout(c, scheme);
     for (int d = 0; d < 3; ++d) s.h[d] = (c.hi[d] - c.lo[d]) / c.n[d];
     const size_t fb = field_bytes(s.L);
     const size_t total = fb * (size_t)s.L.nfields;
@@ -174,7 +196,10 @@ int solve_alloc(Solve& s, const hb_config& c, hipStream_t stream) {
     }
     // zero everything once: the halo stays zero for the life of the solve
     HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
-    for (int k = 0; k < s.L.nfields; ++k) s.f[k] = s.mem + fb * k + (size_t)s.L.origin_off * s.L.esz;
+    int slot = 0;
+    for (int k = 0; k < 9; ++k)
+        if (field_used(k, c.precision, scheme))
+            s.f[k] = s.mem + fb * (size_t)slot++ + (size_t)s.L.origin_off * s.L.esz;
     return HB_OK;
 }
 
@@ -317,7 +342,7 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
     return HB_OK;
 }
 
-// ---- launch group: all solves of one precision, one launch per stage ---------
+// ---- launch group: all solves of one precision share each launch -----------
 
 constexpr int DEFAULT_BY = 16;
 
@@ -329,14 +354,6 @@ int default_zc(const Layout& L, int by) {
     long long zc = std::min<long long>(L.nz, 64);
     while (zc > 8 && xy * ((L.nz + zc - 1) / zc) < 256) zc = (zc + 1) / 2;
     return (int)std::max<long long>(1, zc);
-}
-
-enum Scheme { SCHEME_STEP = 0, SCHEME_PAIRS = 1, SCHEME_STAGES = 2 };
-
-int scheme_of(uint32_t flags) {
-    if (flags & HB_STAGEWISE) return SCHEME_STAGES;
-    if (flags & HB_PAIRWISE) return SCHEME_PAIRS;
-    return SCHEME_STEP;
 }
 
 struct Group {
@@ -617,7 +634,7 @@ size_t hb_footprint(const hb_config* cfg) {
     hb_config c = *cfg;
     c.flags |= HB_ALLOW_UNSTABLE;
     if (validate(&c) != HB_OK) return 0;
-    return solve_footprint(c, 4096);
+    return solve_footprint(c, scheme_of(c.flags), 4096);
 }
 
 int hb_create(const hb_config* cfg, hb_solver** out) {
@@ -633,7 +650,7 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
         h->own_stream = true;
     }
     h->s = std::make_unique<Solve>();
-    HB_TRY(solve_alloc(*h->s, *cfg, h->stream));
+    HB_TRY(solve_alloc(*h->s, *cfg, scheme_of(cfg->flags), h->stream));
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
     h->g.scheme = scheme_of(cfg->flags);
@@ -947,7 +964,11 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
     if (!out) return fail(HB_E_ARG, "out is NULL");
     *out = nullptr;
     if (count < 1 || !cfgs) return fail(HB_E_ARG, "need count >= 1 configs");
-    for (int i = 0; i < count; ++i) HB_TRY(validate(&cfgs[i]));
+    for (int i = 0; i < count; ++i) {
+        HB_TRY(validate(&cfgs[i]));
+        if (scheme_of(cfgs[i].flags) != scheme_of(cfgs[0].flags))
+            return fail(HB_E_ARG, "solve %d selects another scheme than solve 0", i);
+    }
     auto b = std::make_unique<hb_batch>();
     if (stream) {
         b->stream = (hipStream_t)stream;
@@ -959,7 +980,7 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
     b->groups[1].prec = HB_F32C;
     for (int i = 0; i < count; ++i) {
         auto s = std::make_unique<Solve>();
-        HB_TRY(solve_alloc(*s, cfgs[i], b->stream));
+        HB_TRY(solve_alloc(*s, cfgs[i], scheme_of(cfgs[0].flags), b->stream));
         HB_TRY(ensure_ctab(*s, 4096, b->stream, nullptr));
         b->groups[cfgs[i].precision].members.push_back(s.get());
         if (i == 0)
@@ -1094,7 +1115,9 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
     HB_TRY(validate(cfg));
     if (!phi0) return fail(HB_E_ARG, "phi0 is NULL");
     if (steps < 0) return fail(HB_E_ARG, "steps must be >= 0");
-    const size_t need = solve_footprint(*cfg, steps + 1);
+    if (scheme_of(cfg->flags) != SCHEME_STEP)
+        return fail(HB_E_ARG, "pool solves use the whole-step kernel (no HB_PAIRWISE/HB_STAGEWISE)");
+    const size_t need = solve_footprint(*cfg, SCHEME_STEP, steps + 1);
     int free_slot = -1;
     for (size_t i = 0; i < p->slots.size(); ++i)
         if (!p->slots[i].busy) {
@@ -1104,7 +1127,7 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
     if (free_slot < 0) return fail(HB_E_BUSY, "no free slot");
     if (need > p->budget - p->in_use) return fail(HB_E_BUSY, "HBM budget exhausted");
     auto s = std::make_unique<Solve>();
-    HB_TRY(solve_alloc(*s, *cfg, p->stream));
+    HB_TRY(solve_alloc(*s, *cfg, SCHEME_STEP, p->stream));
     HB_TRY(ensure_ctab(*s, steps + 1, p->stream, nullptr));
     HB_TRY(upload_state(*s, 0, 2, phi0, phi1, mem, dtype, p->stream));
     s->nstep = 0;

@@ -36,9 +36,15 @@ def test_footprint_is_host_only(lib):
     from paper_1803_01291_amd import hb
     c = hb.make_config((256, 256, 256), (-16,) * 3, (16,) * 3, 2.0, 1.0, 0.005)
     fp = hb.hb_footprint(c)
-    assert 7 * 256 ** 3 * 8 < fp < 7 * 280 ** 3 * 8
+    # whole-step scheme: Y_phi, Y_psi at two parities, 8 B each
+    assert 4 * 256 ** 3 * 8 < fp < 4 * 280 ** 3 * 8
     c32 = hb.make_config((256, 256, 256), (-16,) * 3, (16,) * 3, 2.0, 1.0, 0.005, precision=hb.HB_F32C)
-    assert hb.hb_footprint(c32) < fp
+    assert 6 * 256 ** 3 * 4 < hb.hb_footprint(c32) < 6 * 280 ** 3 * 4
+    # the stage-pair and per-stage schemes also hold G1..G3
+    for flags in (hb.HB_PAIRWISE, hb.HB_STAGEWISE):
+        cp = hb.make_config((256, 256, 256), (-16,) * 3, (16,) * 3, 2.0, 1.0, 0.005, flags=flags)
+        fields = (hb.hb_footprint(cp) - fp) / (fp / 4)
+        assert abs(fields - 3) < 0.01
     bad = hb.make_config((0, 4, 4), (-1,) * 3, (1,) * 3, 1.0, 1.0, 0.01)
     assert hb.hb_footprint(bad) == 0
 
@@ -54,3 +60,14 @@ def test_plane_size_limit_is_rejected(lib):
                          flags=hb.HB_ALLOW_UNSTABLE)
     assert hb.hb_footprint(big) == 0        # FP64: 2 GiB per plane
     assert "2 GiB" in hb.hb_last_error()
+
+
+def test_batch_with_mixed_schemes_is_rejected(lib):
+    """A batch shares its launches, so every solve must select the same scheme;
+    the check runs before anything touches the device."""
+    from paper_1803_01291_amd import hb
+    a = hb.make_config((16, 16, 16), (-1,) * 3, (1,) * 3, 1.0, 1.0, 0.01)
+    b = hb.make_config((16, 16, 16), (-1,) * 3, (1,) * 3, 1.0, 1.0, 0.01, flags=hb.HB_PAIRWISE)
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_batch_create([a, b])
+    assert e.value.code == hb.HB_E_ARG and "scheme" in str(e.value)

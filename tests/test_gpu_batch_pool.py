@@ -132,6 +132,10 @@ def test_pool_admission_by_footprint(hb):
         assert hb.hb_pool_poll(pool) == [s0]
         hb.hb_pool_release(pool, s0)
         assert hb.hb_pool_admit(pool, cfg, p0, p1, 4) is not None
+        # pool solves run the whole-step kernel: another scheme is an error
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_pool_admit(pool, hb.config_from_workload(w, flags=hb.HB_PAIRWISE), p0, p1, 4)
+        assert e.value.code == hb.HB_E_ARG
     finally:
         hb.hb_pool_destroy(pool)
 
