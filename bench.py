@@ -1,4 +1,4 @@
-"""Benchmark: RK4 grid-point updates/s of the fused FP64 stage kernels.
+"""Benchmark: RK4 grid-point updates/s of the FP64 whole-step kernel.
 
 Workload: 256^3 interior points on [-16,16]^3 (h = 0.125), mu^2 = 2,
 lambda = 1, phi0 = 8 seeded Gaussians (seed 0), phi1 = 0, dt = 0.005 (the
@@ -12,21 +12,25 @@ Prints ONE JSON line.  Extra objects:
                    the 19 field passes of one-pass-per-stage RK4) x points /
                    the kernel's mean duration from HIP events on the solver's
                    stream, against 8 TB/s.  The kernel itself moves only
-                   32 B/point (Y in, Y' out): own_GBps/own_frac price that;
+                   32 B/point (Y in, Y' out): own_GBps/own_frac price that,
+                   own_frac_of_copy against the measured copy ceiling;
                    traffic is the PMC-measured bytes per launch;
   cpu_baseline  -- the FP64 CPU oracle on a bounded number of steps of the
                    same grid, on this host's cores;
-  forms         -- the same step rate for the FP32c form (same grid) when
-                   --forms is given;
-  hbm_probe     -- with --probe, the streamed-bandwidth ceiling measured by
-                   the library's copy and 5-read/2-write probe kernels;
+  forms         -- the same step rate for the FP32c form (same grid);
+  hbm_probe     -- the streamed-bandwidth ceiling measured by the library's
+                   copy and 5-read/2-write probe kernels;
   batched       -- 64 uneven solves (N ~ U{64..192}^3, 500 steps), one
                    whole-step launch per step and precision over all of them,
                    FP64 and FP32c, vs the same solves run one by one;
   served        -- a Poisson request stream (50/s, N in {48..384}^3, 200-2000
                    steps, FP64/FP32c) through the continuous-batching pool:
                    p50/p99 latency and solves/s (offered load is far above
-                   capacity, so latency is mostly queueing).
+                   capacity, so latency is mostly queueing);
+  shard         -- a 512 x 512 x 64 FP64 slab (one GPU's share of 512^3 over
+                   eight), timed like the main leg;
+  radial        -- the batched radial parameter sweep (4096 solves) against
+                   its LDS roofline.
 """
 import argparse
 import json
@@ -269,9 +273,11 @@ def main():
                          "or, for comparison, the stage-pair or per-stage kernels")
     ap.add_argument("--radial-count", type=int, default=4096)
     ap.add_argument("--radial-steps", type=int, default=2000)
-    ap.add_argument("--forms", action="store_true")
-    ap.add_argument("--probe", action="store_true",
-                    help="also measure the streamed-HBM ceiling (copy and 5-read/2-write probes)")
+    ap.add_argument("--forms", action="store_true", help="(on by default)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP32c form of the main leg")
+    ap.add_argument("--probe", action="store_true", help="(on by default)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the streamed-HBM ceiling (copy and 5-read/2-write probes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no "
@@ -326,19 +332,22 @@ def main():
                      "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
     }
-    if args.forms:
+    if not args.no_forms:
         e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
         k32 = sum(ms32)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
                                  "kernel_ms": k32,
                                  "alg_GBps": sum(STAGEWISE_BYTES[1]) * N / (k32 * 1e-3) / 1e9,
                                  "own_GBps": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9}}
-    if args.probe:
+    if not args.no_probe:
         from paper_1803_01291_amd import hb
         gib = 1 << 30
-        out["hbm_probe"] = {"copy_GBps": hb.hb_probe_bandwidth(0, gib, 20),
+        copy = hb.hb_probe_bandwidth(0, gib, 20)
+        out["hbm_probe"] = {"copy_GBps": copy,
                             "read5_write2_GBps": hb.hb_probe_bandwidth(2, gib // 2, 20),
                             "bytes_per_array": [gib, gib // 2]}
+        # the kernel's own bytes against the measured streaming ceiling
+        out["roofline"]["own_frac_of_copy"] = out["roofline"]["own_GBps"] / copy
     if not args.no_batch:
         out["batched"] = run_batch(args.batch_count, args.batch_steps, 16)
     if not args.no_serve:

@@ -250,8 +250,8 @@ int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double
 
 /* ---- measurement ----------------------------------------------------------- */
 
-/* Streamed-bandwidth probe on the current device (the achievable HBM ceiling
- * for kernels shaped like the stage kernels).  kind 0: copy (1 read + 1 write
+/* Streamed-bandwidth probe on the current device (the achievable HBM streaming
+ * ceiling: one 16-byte element per thread per array).  kind 0: copy (1 read + 1 write
  * array), 1: add (2 reads + 1 write), 2: 5 reads + 2 writes (the FP64 stage-4
  * mix).  Each array holds bytes_per_array bytes (library-allocated, freed
  * before return).  *gbps = bytes moved / time of `iters` launches after one

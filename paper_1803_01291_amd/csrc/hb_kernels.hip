@@ -884,8 +884,11 @@ __global__ void pack_kernel(D* __restrict__ dst, int nx, int ny, int nz, long lo
 }
 
 // ---- bandwidth probe: R streamed reads and W streamed writes of 16-byte
-// elements, grid-stride, no reuse (the measured HBM ceiling for kernels shaped
-// like the stage kernels; also the plain copy used to calibrate byte counters)
+// elements, no reuse (the measured HBM streaming ceiling; also the plain copy
+// used to calibrate byte counters).  Launched with one element per thread
+// (a wave moves one contiguous 1 KiB run per array and exits), which measured
+// faster than grid-stride loops of 8-64 blocks per CU, unrolled or not; the
+// loop covers grids capped below one element per thread.
 template <int R, int W>
 __global__ void __launch_bounds__(256)
 probe_kernel(const double2* __restrict__ a0, const double2* __restrict__ a1,

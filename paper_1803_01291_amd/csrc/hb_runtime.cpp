@@ -1253,11 +1253,8 @@ extern "C" int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, d
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (rc == HB_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(HB_E_HIP, "probe events");
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const long long want = (n16 + 255) / 256;
-    const int blocks = (int)std::min<long long>(want, (long long)cus * 16);
+    const int blocks = (int)std::min<long long>(want, 1LL << 30);  // one element per thread
     if (rc == HB_OK) rc = from_hip(launch_probe(kind, in, out, n16, blocks, nullptr), "probe");
     if (rc == HB_OK) rc = from_hip(hipEventRecord(e0, nullptr), "event");
     for (int i = 0; i < iters && rc == HB_OK; ++i)
