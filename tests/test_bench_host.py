@@ -1,0 +1,31 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU rule and the
+bookkeeping behind its traffic figure."""
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""  # no JSON line for a configuration that was not run
+
+
+def test_traffic_constant_matches_the_committed_profile():
+    """bench.py reports PMC-measured traffic only for the sources it was
+    profiled on; the constant and the profile summary must name the same
+    sources and bytes."""
+    import bench
+    prof = open(os.path.join(ROOT, "profiles", "step_kernel_cube256.md")).read()
+    sha = re.search(r"bench\.source_sha\(\)\): `([0-9a-f]+)`", prof).group(1)
+    assert sha == bench.TRAFFIC_SOURCE_SHA
+    # the traffic table's row: raw fetch, scaled fetch, write, total (MiB)
+    row = re.search(r"^\| `step_kernel<double, false, 64, 16>` \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|$",
+                    prof, flags=re.M)
+    assert abs(float(row.group(4)) * 2 ** 20 - bench.TRAFFIC_BYTES_F64) < 0.05 * 2 ** 20
