@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "axis_nodes", "grid_mesh", "gaussian_sum", "cinf_bump", "paper_bump",
     "radial_gaussian", "Workload", "config1", "config2", "config3",
-    "batch_config", "serving_trace", "ServeRequest", "small_case",
+    "batch_config", "serving_trace", "ServeRequest", "small_case", "wide_plane",
 ]
 
 
@@ -263,3 +263,38 @@ def radial_sweep(count: int = 4096, m: int = 1000, dr: float = 5e-4, R: float = 
         phi1[i * m:(i + 1) * m] = a * A * b
         params.append((mu2, lam))
     return phi0, phi1, params
+
+
+def wide_plane(nx: int, ny: int, seed: int = 3, h: float = 0.125, steps: int = 2) -> Workload:
+    """One x-y plane of nx x ny points at spacing h (the box centred on 0,
+    one cell thick), mu^2 = 2, lambda = 1, dt = 0.005, phi1 = 0, and
+    phi0 = f1(x) g1(y) + f2(x) g2(y), each factor a sum of two sinusoids
+    a sin(k s + p) with a ~ U(0.2, 0.6), k ~ U(0.5, 3), p ~ U(0, 2 pi), drawn
+    in that order per sinusoid (f1, g1, f2, g2) from ``default_rng(seed)``.
+    Separable, so planes of 10^8-10^9 points cost little to build."""
+    rng = np.random.default_rng(seed)
+    n = (nx, ny, 1)
+    lo = (-nx * h / 2, -ny * h / 2, -h / 2)
+    hi = (nx * h / 2, ny * h / 2, h / 2)
+    x = axis_nodes(nx, lo[0], hi[0])
+    y = axis_nodes(ny, lo[1], hi[1])
+
+    def factor(s):
+        out = np.zeros_like(s)
+        for _ in range(2):
+            a, k, p = rng.uniform(0.2, 0.6), rng.uniform(0.5, 3.0), rng.uniform(0.0, 2 * np.pi)
+            out += a * np.sin(k * s + p)
+        return out
+
+    f1, g1, f2, g2 = factor(x), factor(y), factor(x), factor(y)
+
+    def phi0():
+        out = np.empty((1, ny, nx))
+        for y0 in range(0, ny, 2048):
+            y1 = min(ny, y0 + 2048)
+            out[0, y0:y1] = g1[y0:y1, None] * f1[None, :] + g2[y0:y1, None] * f2[None, :]
+        return out
+
+    return Workload(f"plane{nx}x{ny}", n, lo, hi, mu2=2.0, lam=1.0, dt=0.005, steps=steps,
+                    phi0=phi0, phi1=_zeros(n))
+
