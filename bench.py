@@ -174,10 +174,7 @@ def run_shard(steps, warmup):
     512 x 512 x 64 (FP64), timed like the main leg; the slab's own zero halo
     stands in for the planes a neighbour would send."""
     import synth_inputs as si
-    w = si.config3()
-    n, lo, hi = (512, 512, 64), (w.lo[0], w.lo[1], -4.0), (w.hi[0], w.hi[1], 4.0)  # middle slab
-    sw = si.Workload("slab512x512x64", n, lo, hi, mu2=w.mu2, lam=w.lam, dt=w.dt, steps=steps,
-                     phi0=lambda: si.cinf_bump(n, lo, hi, 0.8, 10.0), phi1=si._zeros(n))
+    sw = si.slab_config(steps)
     elapsed, stage_ms, _ = run_gpu(sw, 0, steps, warmup, 20)
     return {"grid": [512, 512, 64], "steps": steps,
             "pt_updates_per_s": sw.points * steps / elapsed,

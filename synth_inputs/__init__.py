@@ -33,6 +33,7 @@ __all__ = [
     "axis_nodes", "grid_mesh", "gaussian_sum", "cinf_bump", "paper_bump",
     "radial_gaussian", "Workload", "config1", "config2", "config3",
     "batch_config", "serving_trace", "ServeRequest", "small_case", "wide_plane",
+    "slab_config",
 ]
 
 
@@ -165,6 +166,16 @@ def config3(n: int = 512, steps: int = 1000, L: float = 32.0) -> Workload:
     nn, lo, hi = (n, n, n), (-L,) * 3, (L,) * 3
     return Workload(f"cube{n}_cinfbump", nn, lo, hi, mu2=2.0, lam=1.0, dt=0.005, steps=steps,
                     phi0=lambda: cinf_bump(nn, lo, hi, 0.8, 10.0), phi1=_zeros(nn))
+
+
+def slab_config(steps: int = 200) -> Workload:
+    """One GPU's share of the 512^3 workload under an 8-way z-slab split: the
+    middle slab z in [-4, 4] (64 planes) of config3's box and initial data,
+    512 x 512 x 64 points."""
+    w = config3()
+    n, lo, hi = (512, 512, 64), (w.lo[0], w.lo[1], -4.0), (w.hi[0], w.hi[1], 4.0)
+    return Workload("slab512x512x64", n, lo, hi, mu2=w.mu2, lam=w.lam, dt=w.dt, steps=steps,
+                    phi0=lambda: cinf_bump(n, lo, hi, 0.8, 10.0), phi1=_zeros(n))
 
 
 def small_case(nx: int, ny: int, nz: int, seed: int = 7, steps: int = 10, dt: float = 0.005,

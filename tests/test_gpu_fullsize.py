@@ -6,6 +6,8 @@ default tiling, whole-step kernel).
   nodes, relative to the whole-grid max norm; whole-grid max norms and the
   integral of phi via the GPU's FP64 diagnostics.
 * 256^3 x 10 steps: every node against the oracle run here.
+* 512 x 512 x 64 (the benchmark's shard slab) x 10 steps: every node, FP64
+  and FP32c, against the oracle run here.
 * 512^3 x 1000 steps: FP64 vs the stored oracle samples; FP32c against FP64
   (max and L2 error over the whole grid, and at the samples vs the oracle).
 * 64 uneven solves x 500 steps in one batched launch (graph replay, as timed):
@@ -88,6 +90,19 @@ def test_cube256_10_steps_every_node(hb, oracle_mod):
     err = oracle.rel_maxnorm(phi, psi, *r)
     print(f"256^3 x 10 every node: relative max-norm error {err:.3e}")
     assert err <= 1e-12
+
+
+def test_slab512x512x64_10_steps_every_node(hb, oracle_mod):
+    """The benchmark's shard leg (one GPU's z-slab of the 512^3 workload, its
+    own tiling: 64-plane marches over 387 tiles), every node."""
+    w = si.slab_config()
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        phi, psi, _ = gpu_run(hb, w, 10, precision=prec)
+        if prec == 0:
+            r = oracle.solve_workload(w, nsteps=10)
+        err = oracle.rel_maxnorm(phi, psi, *r)
+        print(f"512x512x64 x 10, precision {prec}, every node: relative max-norm error {err:.3e}")
+        assert err <= tol
 
 
 def test_cube512_fp64_and_fp32c(hb):
