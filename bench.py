@@ -30,7 +30,8 @@ Prints ONE JSON line.  Extra objects:
   shard         -- a 512 x 512 x 64 FP64 slab (one GPU's share of 512^3 over
                    eight), timed like the main leg;
   radial        -- the batched radial parameter sweep (4096 solves) against
-                   its LDS roofline.
+                   its LDS roofline;
+  paper_context -- the paper's own K40c rate (context, not a baseline).
 """
 import argparse
 import json
@@ -298,7 +299,7 @@ def main():
     own = own_b * N / (kernel_ms * 1e-3) / 1e9
     step_alg = sum(STAGEWISE_BYTES[0]) * N
     out = {
-        "metric": "RK4 grid-point updates/s (FP64, fused 13-point stencil stages)",
+        "metric": "RK4 grid-point updates/s + % HBM roofline; batched solves/s, p50/p99 latency",
         "value": rate,
         "unit": "grid-point-updates/s",
         "n_gpus": 1,
@@ -328,6 +329,13 @@ def main():
                      "step_alg_GBps": step_alg / (elapsed / args.steps) / 1e9,
                      "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
+        # the paper's only timing (section 2.1): 27 h to reach t = 50 on one
+        # Tesla K40c, with the default grid and step of section 3 (500^3
+        # points, dt 1e-4: 5e5 RK4 steps), i.e. about 6.4e8 point-updates/s;
+        # another machine and workload, quoted as context only
+        "paper_context": {"value": 500 ** 3 * 5e5 / (27 * 3600.0), "unit": "grid-point-updates/s",
+                          "hardware": "1x Tesla K40c (CUDA Fortran)",
+                          "workload": "500^3, dt 1e-4, 5e5 steps to t = 50 (27 h)"},
     }
     if not args.no_forms:
         e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
