@@ -195,7 +195,8 @@ int hb_batch_destroy(hb_batch* b);
 
 /* ---- served form: continuous batching of admitted solves ------------------ */
 
-/* A pool with an HBM budget (bytes) and at most max_slots resident solves. */
+/* A pool with an HBM budget (bytes, > 0) and at most max_slots resident solves
+ * (1 <= max_slots <= 2^20; HB_E_ARG otherwise).  stream: hipStream_t or NULL. */
 int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out);
 
 /* Admit one solve of `steps` steps with initial data (as hb_set_initial).
@@ -211,7 +212,9 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
  * count); one whole-step launch per step and precision over all of them. */
 int hb_pool_advance(hb_pool* p, int k);
 
-/* Slots that finished since the last poll (up to cap); *ndone is the count. */
+/* Slots that finished since the last poll, written to done[0 .. cap-1] (done
+ * may be NULL only when cap <= 0); *ndone is the count.  A finished slot is
+ * reported once. */
 int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone);
 
 /* Number of admitted, unfinished solves and bytes of the budget in use. */

@@ -12,6 +12,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -54,6 +55,22 @@ int from_hip(int e, const char* what) {
 }
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+// Step counts and indices are capped so that step arithmetic and the
+// coefficient table's size cannot overflow (2^40 steps would already need a
+// 35 TB table).
+constexpr long long MAX_STEPS = 1LL << 40;
+
+// device allocation; a failure is HB_E_NOMEM and leaves no sticky HIP error
+int dev_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(HB_E_NOMEM, "%s (%zu bytes): device allocation failed", what, bytes);
+    }
+    return HB_OK;
+}
 
 // ---- layout ------------------------------------------------------------------
 
@@ -222,16 +239,23 @@ int ensure_ctab(Solve& s, long long need, hipStream_t stream, bool* reallocated)
     if (reallocated) *reallocated = false;
     if (need <= s.ctab_steps) return HB_OK;
     const long long cap = ctab_capacity(need, s.ctab_steps);
+    // the table holds 4 doubles per step from step 0, so its size follows the
+    // caller's step count: a count too large for host memory is HB_E_NOMEM
     std::vector<double> host;
-    fill_ctab(s.cfg, 0, cap, host);
-    double* nt = nullptr;
-    hipError_t e = hipMalloc((void**)&nt, host.size() * sizeof(double));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(HB_E_NOMEM, "coefficient table allocation failed");
+    try {
+        fill_ctab(s.cfg, 0, cap, host);
+    } catch (const std::bad_alloc&) {
+        return fail(HB_E_NOMEM, "coefficient table for %lld steps: host allocation failed", cap);
     }
-    HIP_TRY(hipStreamSynchronize(stream));
-    HIP_TRY(hipMemcpy(nt, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+    double* nt = nullptr;
+    HB_TRY(dev_alloc((void**)&nt, host.size() * sizeof(double), "coefficient table"));
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(nt, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(nt);
+        return fail(HB_E_HIP, "coefficient table upload: %s", hipGetErrorString(e));
+    }
     if (s.ctab) HIP_TRY(hipFree(s.ctab));
     s.ctab = nt;
     s.ctab_steps = cap;
@@ -289,7 +313,7 @@ int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const vo
         const void* dsrc = src[k];
         void* staged = nullptr;
         if (src[k] && mem == HB_HOST) {
-            HIP_TRY(hipMalloc(&staged, bytes));
+            HB_TRY(dev_alloc(&staged, bytes, "staging buffer"));
             hipError_t e = hipMemcpyAsync(staged, src[k], bytes, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) {
                 (void)hipFree(staged);
@@ -327,7 +351,7 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
                             "pack"));
         } else {
             void* staged = nullptr;
-            HIP_TRY(hipMalloc(&staged, bytes));
+            HB_TRY(dev_alloc(&staged, bytes, "staging buffer"));
             int r = launch_pack(s.prec(), dtype, staged, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, hi[k],
                                 lo[k], stream);
             hipError_t e = r ? (hipError_t)r : hipMemcpyAsync(dst[k], staged, bytes,
@@ -594,9 +618,10 @@ int set_targets(Group& g, long long extra, hipStream_t stream, bool* tables_move
     bool moved = false;
     for (size_t i = 0; i < g.members.size(); ++i) {
         Solve* s = g.members[i];
-        s->target = s->nstep + extra;
+        const long long target = s->nstep + extra;
         bool re = false;
-        HB_TRY(ensure_ctab(*s, s->target, stream, &re));
+        HB_TRY(ensure_ctab(*s, target, stream, &re));
+        s->target = target;
         moved = moved || re;
     }
     if (tables_moved) *tables_moved = moved;
@@ -670,7 +695,7 @@ static int solver_rebuild(hb_solver* h) {
 int hb_set_state(hb_solver* h, const void* phi, const void* psi, int64_t n, int mem, int dtype) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
     if (!phi) return fail(HB_E_ARG, "phi is NULL");
-    if (n < 0) return fail(HB_E_ARG, "step index must be >= 0");
+    if (n < 0 || n > MAX_STEPS) return fail(HB_E_ARG, "step index must be in [0, 2^40]");
     Solve& s = *h->s;
     const int par = (int)(n & 1);
     HB_TRY(upload_state(s, 0 + par, 2 + par, phi, psi, mem, dtype, h->stream));
@@ -688,7 +713,7 @@ int hb_set_initial(hb_solver* h, const void* phi0, const void* phi1, int mem, in
 
 int hb_step(hb_solver* h, int64_t nsteps) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
-    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    if (nsteps < 0 || nsteps > MAX_STEPS) return fail(HB_E_ARG, "nsteps must be in [0, 2^40]");
     if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
     if (nsteps == 0) return HB_OK;
     bool moved = false;
@@ -700,7 +725,7 @@ int hb_step(hb_solver* h, int64_t nsteps) {
 
 int hb_step_timed(hb_solver* h, int64_t nsteps, double* stage_ms) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
-    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    if (nsteps < 0 || nsteps > MAX_STEPS) return fail(HB_E_ARG, "nsteps must be in [0, 2^40]");
     if (!h->s->has_initial) return fail(HB_E_STATE, "no initial data");
     bool moved = false;
     HB_TRY(set_targets(h->g, nsteps, h->stream, &moved));
@@ -734,10 +759,13 @@ int hb_diagnostics(hb_solver* h, hb_diag* out) {
     Solve& s = *h->s;
     if (!s.has_initial) return fail(HB_E_STATE, "no initial data");
     if (!h->built) HB_TRY(solver_rebuild(h));
-    if (!h->d_partials) {
+    if (!h->d_partials || !h->d_diag) {  // both, or again after a failed allocation
+        if (h->d_partials) (void)hipFree(h->d_partials);
+        h->d_partials = nullptr;
         h->nparts = diag_partials_needed(s.L.nx, s.L.ny, s.L.nz);
-        HIP_TRY(hipMalloc((void**)&h->d_partials, (size_t)h->nparts * DIAG_COUNT * sizeof(double)));
-        HIP_TRY(hipMalloc((void**)&h->d_diag, DIAG_COUNT * sizeof(double)));
+        HB_TRY(dev_alloc((void**)&h->d_partials, (size_t)h->nparts * DIAG_COUNT * sizeof(double),
+                         "diagnostics partials"));
+        HB_TRY(dev_alloc((void**)&h->d_diag, DIAG_COUNT * sizeof(double), "diagnostics"));
     }
     const double t = s.cfg.t0 + (double)s.nstep * s.cfg.dt;
     const double c = std::exp(-2.0 * t) * s.cfg.inv_L2;
@@ -840,7 +868,7 @@ int snapshot_take(Group& g, Snapshot& snap, hipStream_t stream) {
         const int nf = s->prec() == HB_F32C ? 4 : 2;
         for (int k = 0; k < nf; ++k) {
             void* b = nullptr;
-            HIP_TRY(hipMalloc(&b, fb));
+            HB_TRY(dev_alloc(&b, fb, "autotune snapshot"));
             snap.bufs.push_back(b);
             char* base = (char*)s->f[idx[k]] - (size_t)s->L.origin_off * s->L.esz;
             HIP_TRY(hipMemcpyAsync(b, base, fb, hipMemcpyDeviceToDevice, stream));
@@ -1010,7 +1038,7 @@ int hb_batch_set_initial(hb_batch* b, int i, const void* phi0, const void* phi1,
 
 int hb_batch_step(hb_batch* b, int64_t nsteps) {
     if (!b) return fail(HB_E_ARG, "batch is NULL");
-    if (nsteps < 0) return fail(HB_E_ARG, "nsteps must be >= 0");
+    if (nsteps < 0 || nsteps > MAX_STEPS) return fail(HB_E_ARG, "nsteps must be in [0, 2^40]");
     for (auto& s : b->solves)
         if (!s->has_initial) return fail(HB_E_STATE, "a solve has no initial data");
     if (nsteps == 0) return HB_OK;
@@ -1091,7 +1119,8 @@ int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out
     g_last_error.clear();
     if (!out) return fail(HB_E_ARG, "out is NULL");
     *out = nullptr;
-    if (max_slots < 1 || hbm_budget == 0) return fail(HB_E_ARG, "need max_slots >= 1 and a budget");
+    if (max_slots < 1 || max_slots > (1 << 20) || hbm_budget == 0)
+        return fail(HB_E_ARG, "need 1 <= max_slots <= 2^20 and a budget");
     auto p = std::make_unique<hb_pool>();
     p->slots.resize(max_slots);
     p->budget = hbm_budget;
@@ -1114,7 +1143,7 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
     *slot = -1;
     HB_TRY(validate(cfg));
     if (!phi0) return fail(HB_E_ARG, "phi0 is NULL");
-    if (steps < 0) return fail(HB_E_ARG, "steps must be >= 0");
+    if (steps < 0 || steps > MAX_STEPS) return fail(HB_E_ARG, "steps must be in [0, 2^40]");
     if (scheme_of(cfg->flags) != SCHEME_STEP)
         return fail(HB_E_ARG, "pool solves use the whole-step kernel (no HB_PAIRWISE/HB_STAGEWISE)");
     const size_t need = solve_footprint(*cfg, SCHEME_STEP, steps + 1);
@@ -1177,7 +1206,7 @@ int hb_pool_advance(hb_pool* p, int k) {
 }
 
 int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone) {
-    if (!p || !ndone) return fail(HB_E_ARG, "NULL argument");
+    if (!p || !ndone || (cap > 0 && !done)) return fail(HB_E_ARG, "NULL argument");
     int n = 0;
     for (size_t i = 0; i < p->slots.size(); ++i) {
         auto& sl = p->slots[i];

@@ -158,6 +158,35 @@ def _arr(a):
     raise TypeError(f"unsupported array type {type(a)}")
 
 
+# Points of every live grid, keyed by ("s", solver), ("b", batch, index) or
+# ("p", pool, slot): the C ABI takes no array sizes, so the binding checks
+# them before a kernel could read or write past a caller's array.
+_GRIDS: dict = {}
+
+
+def _points(cfg) -> int:
+    return int(cfg.n[0]) * int(cfg.n[1]) * int(cfg.n[2])
+
+
+def _pair(key, a, b, what):
+    """Marshal one or two state arrays of the grid `key` (each may be None):
+    (ptr_a, ptr_b, mem, dtype, keepalive).  Both must hold the grid's number of
+    points and share memory kind and dtype."""
+    if key not in _GRIDS:
+        raise ValueError(f"{what}: unknown or destroyed handle")
+    count = _GRIDS[key]
+    ma, mb = _arr(a), _arr(b)
+    for x in (a, b):
+        if x is not None:
+            n = x.size if isinstance(x, np.ndarray) else x.numel()
+            if n != count:
+                raise ValueError(f"{what}: array has {n} values, the grid has {count}")
+    if a is not None and b is not None and ma[1:3] != mb[1:3]:
+        raise ValueError(f"{what}: both arrays must share memory kind and dtype")
+    mem, dt = (ma[1], ma[2]) if a is not None else (mb[1], mb[2])
+    return ma[0], mb[0], mem, dt, (ma[3], mb[3])
+
+
 def make_config(n: Sequence[int], lo: Sequence[float], hi: Sequence[float], mu2: float,
                 lam: float, dt: float, t0: float = 0.0, inv_L2: float = 1.0,
                 precision: int = HB_F64, flags: int = 0, stream: Optional[int] = None) -> hb_config:
@@ -179,23 +208,22 @@ def config_from_workload(w, precision: int = HB_F64, flags: int = 0, stream=None
 def hb_create(cfg: hb_config) -> int:
     h = _P()
     _check(load().hb_create(ctypes.byref(cfg), ctypes.byref(h)))
+    _GRIDS[("s", h.value)] = _points(cfg)
     return h.value
 
 
 def hb_set_initial(h: int, phi0, phi1=None) -> None:
-    p0, m0, d0, _k0 = _arr(phi0)
-    p1, m1, d1, _k1 = _arr(phi1)
-    if phi1 is not None and (m0, d0) != (m1, d1):
-        raise ValueError("phi0 and phi1 must share memory kind and dtype")
-    _check(load().hb_set_initial(h, p0, p1, m0, d0))
+    if phi0 is None:
+        raise ValueError("hb_set_initial: phi0 is required")
+    p0, p1, m, d, _keep = _pair(("s", h), phi0, phi1, "hb_set_initial")
+    _check(load().hb_set_initial(h, p0, p1, m, d))
 
 
 def hb_set_state(h: int, phi, psi, n: int) -> None:
-    p0, m0, d0, _k0 = _arr(phi)
-    p1, m1, d1, _k1 = _arr(psi)
-    if psi is not None and (m0, d0) != (m1, d1):
-        raise ValueError("phi and psi must share memory kind and dtype")
-    _check(load().hb_set_state(h, p0, p1, int(n), m0, d0))
+    if phi is None:
+        raise ValueError("hb_set_state: phi is required")
+    p0, p1, m, d, _keep = _pair(("s", h), phi, psi, "hb_set_state")
+    _check(load().hb_set_state(h, p0, p1, int(n), m, d))
 
 
 def hb_step(h: int, nsteps: int) -> None:
@@ -210,13 +238,9 @@ def hb_step_timed(h: int, nsteps: int):
 
 def hb_read(h: int, phi=None, phi_t=None) -> None:
     """Fill the given output arrays (NumPy host or torch device)."""
-    ref = phi if phi is not None else phi_t
-    if ref is None:
+    if phi is None and phi_t is None:
         return
-    p0, m, d, _k0 = _arr(phi)
-    p1, m1, d1, _k1 = _arr(phi_t)
-    if phi is None:
-        m, d = m1, d1
+    p0, p1, m, d, _keep = _pair(("s", h), phi, phi_t, "hb_read")
     _check(load().hb_read(h, p0, p1, m, d))
 
 
@@ -252,6 +276,7 @@ def hb_autotune(h: int, trial_steps: int = 5):
 
 def hb_destroy(h: int) -> None:
     if h:
+        _GRIDS.pop(("s", h), None)
         _check(load().hb_destroy(h))
 
 
@@ -269,13 +294,16 @@ def hb_batch_create(cfgs: Sequence[hb_config], stream=None) -> int:
     arr = (hb_config * len(cfgs))(*cfgs)
     b = _P()
     _check(load().hb_batch_create(len(cfgs), arr, stream, ctypes.byref(b)))
+    for i, c in enumerate(cfgs):
+        _GRIDS[("b", b.value, i)] = _points(c)
     return b.value
 
 
 def hb_batch_set_initial(b: int, i: int, phi0, phi1=None) -> None:
-    p0, m0, d0, _k0 = _arr(phi0)
-    p1, _m1, _d1, _k1 = _arr(phi1)
-    _check(load().hb_batch_set_initial(b, int(i), p0, p1, m0, d0))
+    if phi0 is None:
+        raise ValueError("hb_batch_set_initial: phi0 is required")
+    p0, p1, m, d, _keep = _pair(("b", b, int(i)), phi0, phi1, "hb_batch_set_initial")
+    _check(load().hb_batch_set_initial(b, int(i), p0, p1, m, d))
 
 
 def hb_batch_step(b: int, nsteps: int) -> None:
@@ -283,10 +311,9 @@ def hb_batch_step(b: int, nsteps: int) -> None:
 
 
 def hb_batch_read(b: int, i: int, phi=None, phi_t=None) -> None:
-    p0, m, d, _k0 = _arr(phi)
-    p1, m1, d1, _k1 = _arr(phi_t)
-    if phi is None:
-        m, d = m1, d1
+    if phi is None and phi_t is None:
+        return
+    p0, p1, m, d, _keep = _pair(("b", b, int(i)), phi, phi_t, "hb_batch_read")
     _check(load().hb_batch_read(b, int(i), p0, p1, m, d))
 
 
@@ -298,8 +325,14 @@ def hb_batch_set_tiling(b: int, by: int, zc: int) -> None:
     _check(load().hb_batch_set_tiling(b, int(by), int(zc)))
 
 
+def _forget(kind, handle):
+    for k in [k for k in _GRIDS if k[0] == kind and k[1] == handle]:
+        del _GRIDS[k]
+
+
 def hb_batch_destroy(b: int) -> None:
     if b:
+        _forget("b", b)
         _check(load().hb_batch_destroy(b))
 
 
@@ -313,13 +346,20 @@ def hb_pool_create(hbm_budget: int, max_slots: int, stream=None) -> int:
 
 def hb_pool_admit(p: int, cfg: hb_config, phi0, phi1, steps: int) -> Optional[int]:
     """Returns the slot, or None when the pool is busy (HB_E_BUSY)."""
-    p0, m0, d0, _k0 = _arr(phi0)
-    p1, _m1, _d1, _k1 = _arr(phi1)
+    if phi0 is None:
+        raise ValueError("hb_pool_admit: phi0 is required")
+    key = ("p", p, None)
+    _GRIDS[key] = _points(cfg)
+    try:
+        p0, p1, m, d, _keep = _pair(key, phi0, phi1, "hb_pool_admit")
+    finally:
+        del _GRIDS[key]
     slot = _I()
-    rc = load().hb_pool_admit(p, ctypes.byref(cfg), p0, p1, m0, d0, int(steps), ctypes.byref(slot))
+    rc = load().hb_pool_admit(p, ctypes.byref(cfg), p0, p1, m, d, int(steps), ctypes.byref(slot))
     if rc == HB_E_BUSY:
         return None
     _check(rc)
+    _GRIDS[("p", p, slot.value)] = _points(cfg)
     return slot.value
 
 
@@ -342,19 +382,20 @@ def hb_pool_stats(p: int):
 
 
 def hb_pool_read(p: int, slot: int, phi=None, phi_t=None) -> None:
-    p0, m, d, _k0 = _arr(phi)
-    p1, m1, d1, _k1 = _arr(phi_t)
-    if phi is None:
-        m, d = m1, d1
+    if phi is None and phi_t is None:
+        return
+    p0, p1, m, d, _keep = _pair(("p", p, int(slot)), phi, phi_t, "hb_pool_read")
     _check(load().hb_pool_read(p, int(slot), p0, p1, m, d))
 
 
 def hb_pool_release(p: int, slot: int) -> None:
     _check(load().hb_pool_release(p, int(slot)))
+    _GRIDS.pop(("p", p, int(slot)), None)
 
 
 def hb_pool_destroy(p: int) -> None:
     if p:
+        _forget("p", p)
         _check(load().hb_pool_destroy(p))
 
 
@@ -398,6 +439,13 @@ def hb_radial_solve(cfgs, phi, psi, stream=None) -> None:
     """Advance the solves in place; phi/psi: FP64 NumPy arrays (host) or torch
     tensors (device) holding the solves back to back."""
     arr = (hb_radial_config * len(cfgs))(*cfgs)
+    if phi is None or psi is None:
+        raise ValueError("hb_radial_solve: phi and psi are required")
+    total = sum(int(c.m) for c in cfgs)
+    for x in (phi, psi):
+        n = x.size if isinstance(x, np.ndarray) else x.numel()
+        if n != total:
+            raise ValueError(f"hb_radial_solve: array has {n} values, the solves have {total} nodes")
     p0, m0, d0, _k0 = _arr(phi)
     p1, m1, d1, _k1 = _arr(psi)
     if d0 != HB_DTYPE_F64 or d1 != HB_DTYPE_F64 or m0 != m1:

@@ -71,3 +71,35 @@ def test_batch_with_mixed_schemes_is_rejected(lib):
     with pytest.raises(hb.HBError) as e:
         hb.hb_batch_create([a, b])
     assert e.value.code == hb.HB_E_ARG and "scheme" in str(e.value)
+
+
+def test_pool_slot_count_is_bounded(lib):
+    """A slot table sized by the caller is bounded (HB_E_ARG before anything is
+    allocated or touches the device)."""
+    from paper_1803_01291_amd import hb
+    for slots in (0, (1 << 20) + 1):
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_pool_create(1 << 30, slots)
+        assert e.value.code == hb.HB_E_ARG
+
+
+def test_binding_rejects_wrong_array_sizes(lib):
+    """The C ABI takes no array sizes; the binding checks them against the grid
+    before any call that would read or write the caller's memory."""
+    from paper_1803_01291_amd import hb
+    import numpy as np
+    hb._GRIDS[("s", 12345)] = 4 * 5 * 6   # a grid the binding knows (no device call follows)
+    try:
+        with pytest.raises(ValueError, match="120"):
+            hb.hb_set_initial(12345, np.zeros(119))
+        with pytest.raises(ValueError, match="120"):
+            hb.hb_read(12345, np.zeros(120), np.zeros(121))
+        with pytest.raises(ValueError, match="share"):
+            hb.hb_read(12345, np.zeros(120), np.zeros(120, np.float32))
+    finally:
+        del hb._GRIDS[("s", 12345)]
+    with pytest.raises(ValueError, match="unknown"):
+        hb.hb_set_initial(99999, np.zeros(8))
+    cfg = hb.make_radial_config(100, 1e-3, 1.0, 1.0, 1e-5, 1)
+    with pytest.raises(ValueError, match="nodes"):
+        hb.hb_radial_solve([cfg, cfg], np.zeros(150), np.zeros(200))

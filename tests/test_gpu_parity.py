@@ -222,6 +222,17 @@ def test_errors(hb):
         with pytest.raises(hb.HBError) as e:
             hb.hb_step(h, 1)
         assert e.value.code == hb.HB_E_STATE
+        p0, p1 = w.initial()
+        # step counts and indices are capped at 2^40 (no overflow, no huge table)
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_set_state(h, p0, p1, 2 ** 41)
+        assert e.value.code == hb.HB_E_ARG
+        hb.hb_set_initial(h, p0, p1)
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_step(h, 2 ** 41)
+        assert e.value.code == hb.HB_E_ARG
+        hb.hb_step(h, 1)  # still usable
+        assert hb.hb_time(h)[1] == 1
     finally:
         hb.hb_destroy(h)
     bad = hb.config_from_workload(w)
