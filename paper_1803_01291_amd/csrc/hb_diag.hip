@@ -27,7 +27,7 @@ template <bool COMP>
 __global__ void __launch_bounds__(DIAG_THREADS)
 diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restrict__ partials) {
     const int nx = d->nx, ny = d->ny, nz = d->nz;
-    const long long sy = d->sy, sz = d->sz;
+    const long long sy = d->sy, sz = d->sz, cs = d->cs;  // cs elements per cell
     const void* P = d->y_phi[par];
     const void* S = d->y_psi[par];
     const float* LP = d->lo_phi;
@@ -39,11 +39,11 @@ diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restri
     for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
         const int y = (int)(row % ny), z = (int)(row / ny);
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const long long o = (long long)z * sz + (long long)y * sy + x;
+            const long long o = ((long long)z * sz + (long long)y * sy + x) * cs;
             const double p = fld<COMP>(P, LP, o);
             const double s = fld<COMP>(S, LS, o);
             double lap = w0 * p;
-            const long long st[3] = {1, sy, sz};
+            const long long st[3] = {cs, sy * cs, sz * cs};
             for (int a = 0; a < 3; ++a) {
                 lap += d->w1[a] * (fld<COMP>(P, LP, o - st[a]) + fld<COMP>(P, LP, o + st[a]));
                 lap += d->w2[a] * (fld<COMP>(P, LP, o - 2 * st[a]) + fld<COMP>(P, LP, o + 2 * st[a]));

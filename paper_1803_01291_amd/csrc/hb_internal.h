@@ -1,12 +1,16 @@
 // Internal layouts shared by the HIP kernels and the host runtime of libhb.
 //
 // Field layout in HBM (one allocation per solve, all fields alike):
-//   element (x, y, z), x in [-2, nx+2), y in [-2, ny+2), z in [-2, nz+2),
-//   lives at origin + z*sz + y*sy + x, where origin is the interior point
-//   (0, 0, 0).  The row pitch sy is nx+4 rounded up to a 128-byte multiple and
-//   origin sits on a 128-byte boundary, so every interior row starts aligned;
-//   the 2-cell halo (the zero boundary condition) is zeroed once at creation
-//   and never written afterwards.
+//   cell (x, y, z), x in [-2, nx+2), y in [-2, ny+2), z in [-2, nz+2), holds
+//   its value at element cs * (z*sz + y*sy + x) from the field's origin (the
+//   interior point (0, 0, 0)).  cs = 1 for separate fields; cs = 2 for the
+//   paired state of whole-step solves, where one field holds (phi, psi) per
+//   cell (FP32c: the high parts in one paired field, the low parts in
+//   another), so a cell's state moves in one 16-byte (8-byte) access; the psi
+//   view of a paired field is its phi view plus one element.  The row pitch
+//   sy is nx+4 rounded up to a 128-byte multiple of cells and cell (-2, y, z)
+//   starts a 128-byte line.  The 2-cell halo (the zero boundary condition) is
+//   zeroed once at creation and never written afterwards.
 #pragma once
 
 #include <stdint.h>
@@ -19,13 +23,15 @@ enum : int { PREC_F64 = 0, PREC_F32C = 1 };
 // One solve as the stage kernels see it (device resident, 128-byte aligned).
 struct SolveDesc {
     void* y_phi[2];      // state phi (FP64) or its FP32 high part, ping-pong by step parity
-    void* y_psi[2];      // state psi, same
-    void* g[3];          // psi-forcing of stages 1..3 (G1, G2, G3)
+    void* y_psi[2];      // state psi, same (paired: y_phi[p] + one element)
+    void* g[3];          // psi-forcing of stages 1..3 (G1, G2, G3; separate fields only)
     float* lo_phi;       // FP32c: low parts of the compensated state (updated in place)
-    float* lo_psi;
+    float* lo_psi;       // (paired: lo_phi + one element)
     const double* ctab;  // c(t) per stage: ctab[4 n + s], s = 0..3
-    long long sy, sz;    // row and plane pitch in elements
+    long long sy, sz;    // row and plane pitch in cells
     int nx, ny, nz, prec;
+    int cs;              // elements per cell: 1 (separate fields) or 2 (paired state)
+    int pad0_;
     double w0;           // -5/2 (1/hx^2 + 1/hy^2 + 1/hz^2)
     double w1[3];        // 4/3 / h_d^2
     double w2[3];        // -1/12 / h_d^2
@@ -51,11 +57,11 @@ int launch_stage(int prec, int stage, int by, const SolveDesc* descs, const Tile
 // (writes the next state).  Bitwise equal to the four per-stage launches.
 int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream);
-// Whole-step kernel: one launch per RK4 step.  A block's threads own an
-// rx x ry region: its interior tile of (rx - 4) x (ry - 4) columns plus a
-// 2-cell ring.  Shapes (`shape` indexes this table), both 16 waves per CU:
-// 36 x 28 (1008 threads; tiles 32 columns wide, so x-tiles start on 128-byte
-// lines and cover power-of-two widths exactly) and 64 x 16 (1024 threads).
+// Whole-step kernel: one launch per RK4 step, on paired-state solves (cs = 2).
+// A block's threads own an rx x ry region: its interior tile of
+// (rx - 4) x (ry - 4) columns plus a 2-cell ring.  Shapes (`shape` indexes
+// this table), both 16 waves per CU: 36 x 28 (1008 threads; tiles 32 columns
+// wide, which cover power-of-two widths exactly) and 64 x 16 (1024 threads).
 // Bitwise equal to the stage-pair kernels.
 struct StepShape {
     int rx, ry, blocks_per_cu;
@@ -68,13 +74,13 @@ int launch_set_target(SolveDesc* descs, int index, long long target, void* strea
 int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream);
 
 // Contiguous user array [nz][ny][nx] of src_dtype (0 = f64, 1 = f32) into a
-// pitched field.  FP64 fields take the value; FP32c fields take
+// pitched field (cs elements per cell).  FP64 fields take the value; FP32c fields take
 // hi = (float)v and lo = (float)(v - hi).  `src` may be NULL for zeros.
 int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,
-                  long long sz, void* hi, float* lo, void* stream);
+                  long long sz, int cs, void* hi, float* lo, void* stream);
 // Pitched field into a contiguous user array of dst_dtype (FP32c: hi + lo in FP64).
 int launch_pack(int prec, int dst_dtype, void* dst, int nx, int ny, int nz, long long sy,
-                long long sz, const void* hi, const float* lo, void* stream);
+                long long sz, int cs, const void* hi, const float* lo, void* stream);
 
 // Diagnostics: per-block partials then one fixed-order final pass (deterministic).
 enum { DIAG_SUM_PHI = 0, DIAG_SUM_PHI2, DIAG_SUM_PSI2, DIAG_MAX_PHI, DIAG_MAX_PSI, DIAG_MAX_LAP,

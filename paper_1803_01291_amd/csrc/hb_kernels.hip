@@ -98,6 +98,30 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, T
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
 }
 
+// A paired cell (phi, psi) in one access: 16 bytes (FP64) or 8 bytes (FP32).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using pair_t = T __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ pair_t<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(pair_t<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    else
+        return __builtin_bit_cast(pair_t<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t off, T a, T b) {
+    pair_t<T> v;
+    v.x = a;
+    v.y = b;
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
 // ---- per-point arithmetic shared by every kernel ----
 // Written as explicit operations (fused multiply-adds where named), with
 // contraction off, in one fixed order, so the per-stage, stage-pair and
@@ -567,12 +591,13 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     if (n >= d->target) return;  // uniform over the block
     const int par = (int)(n & 1);
 
-    const T* __restrict__ Yp = (const T*)d->y_phi[par];
-    const T* __restrict__ Ys = (const T*)d->y_psi[par];
-    T* __restrict__ Op = (T*)d->y_phi[par ^ 1];
-    T* __restrict__ Os = (T*)d->y_psi[par ^ 1];
+    // paired state: (phi, psi) of a cell side by side (FP32c: the high parts;
+    // the low parts in a second paired field)
+    const T* __restrict__ Y = (const T*)d->y_phi[par];
+    T* __restrict__ O = (T*)d->y_phi[par ^ 1];
     const long long sy = d->sy, sz = d->sz;
     const int nx = d->nx, ny = d->ny, nz = d->nz;
+    constexpr int CB = 2 * sizeof(T);  // bytes per cell
 
     const T c1 = (T)ldg(d->ctab, 4 * n + 0, true), c2 = (T)ldg(d->ctab, 4 * n + 1, true);
     const T c3 = (T)ldg(d->ctab, 4 * n + 2, true), c4 = (T)ldg(d->ctab, 4 * n + 3, true);
@@ -594,18 +619,16 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     // plane, measured from the plane's cell (-2, -2); a plane is under 2 GiB.
     auto col_bytes = [&](int x, int y) -> uint32_t {
         const int cx = min(max(x, -2), nx + 1), cy = min(max(y, -2), ny + 1);
-        return (uint32_t)(((long long)(cy + 2) * sy + (cx + 2)) * (long long)sizeof(T));
+        return (uint32_t)(((long long)(cy + 2) * sy + (cx + 2)) * (long long)CB);
     };
     const uint32_t col_b = col_bytes(gx, gy);
     // plane p of a field starts (at its cell (-2, -2)) p * pbytes bytes past
     // the field's corner address; the products are 32 x 32 -> 64-bit scalar
     // multiplies and the bases scalar adds
-    const int pbytes = (int)(sz * (long long)sizeof(T));
-    const long long cb = (2 * sy + 2) * (long long)sizeof(T);
-    const unsigned long long bYp = (unsigned long long)Yp - cb, bYs = (unsigned long long)Ys - cb;
-    const unsigned long long bOp = (unsigned long long)Op - cb, bOs = (unsigned long long)Os - cb;
-    const unsigned long long bLp = (unsigned long long)d->lo_phi - cb;
-    const unsigned long long bLs = (unsigned long long)d->lo_psi - cb;
+    const int pbytes = (int)(sz * (long long)CB);
+    const long long cb = (2 * sy + 2) * (long long)CB;
+    const unsigned long long bY = (unsigned long long)Y - cb, bO = (unsigned long long)O - cb;
+    const unsigned long long bL = (unsigned long long)d->lo_phi - cb;
     auto poff = [&](int p) -> unsigned long long { return (unsigned long long)((long long)p * pbytes); };
     auto rs = [&](unsigned long long b, unsigned long long off) { return plane_rsrc(b + off, pbytes); };
     auto clampz = [&](int p) { return min(max(p, -2), nz + 1); };
@@ -659,15 +682,15 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     // those of every later pass
     auto ld_own = [&](int k) {
         const int p = zbase - 2 + k;
-        const unsigned long long o = poff(clampz(p));
-        qp[(k + 4) % 6] = bload<T>(rs(bYp, o), col_b);
-        qs[(k + 4) % 6] = bload<T>(rs(bYs, o), col_b);
+        const pair_t<T> v = bload2<T>(rs(bY, poff(clampz(p))), col_b);
+        qp[(k + 4) % 6] = v.x;
+        qs[(k + 4) % 6] = v.y;
     };
     auto ld_outer = [&](int k) {
         const int p = zbase + k;
-        const unsigned long long o = poff(clampz(p));
-        opr[k] = bload<T>(rs(bYp, o), outer_b);
-        osr[k] = bload<T>(rs(bYs, o), outer_b);
+        const pair_t<T> v = bload2<T>(rs(bY, poff(clampz(p))), outer_b);
+        opr[k] = v.x;
+        osr[k] = v.y;
     };
     ld_own(0);
     ld_own(1);
@@ -776,12 +799,8 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             // never dereferenced even where z is outside the field)
             const uint32_t ob = zout ? out_b : BUF_SKIP;
             const unsigned long long o = poff(z);
-            bstore<T>(rs(bOp, o), ob, op_);
-            bstore<T>(rs(bOs, o), ob, os_);
-            if constexpr (COMP) {
-                bstore<float>(rs(bLp, o), ob, ol_p);
-                bstore<float>(rs(bLs, o), ob, ol_s);
-            }
+            bstore2<T>(rs(bO, o), ob, op_, os_);
+            if constexpr (COMP) bstore2<float>(rs(bL, o), ob, ol_p, ol_s);
         }
 
         // ---- loads for later planes, into the slots this plane freed ----
@@ -789,19 +808,19 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         // clamped and the value is never used)
         // own plane zi+4 into the slot of plane zi-2 (last used just above);
         // zi+4 >= z0+2 >= 2, and planes past nz+1 are never needed
-        const unsigned long long op4 = poff(min(zi + 4, zlast));
-        qp[Q(4)] = bload<T>(rs(bYp, op4), col_b);
-        qs[Q(4)] = bload<T>(rs(bYs, op4), col_b);
+        const pair_t<T> v4 = bload2<T>(rs(bY, poff(min(zi + 4, zlast))), col_b);
+        qp[Q(4)] = v4.x;
+        qs[Q(4)] = v4.y;
         // outer plane zi+3 into the slot of plane zi (used before the barrier)
-        const unsigned long long oq3 = poff(min(zi + 3, z1 + 1));
-        opr[OS] = bload<T>(rs(bYp, oq3), outer_b);
-        osr[OS] = bload<T>(rs(bYs, oq3), outer_b);
+        const pair_t<T> v3 = bload2<T>(rs(bY, poff(min(zi + 3, z1 + 1))), outer_b);
+        opr[OS] = v3.x;
+        osr[OS] = v3.y;
         if constexpr (COMP) {
             // low parts of output plane zi (updated two planes from now);
             // the slot held output plane zi-3's, used one plane ago
-            const unsigned long long ol = poff(min(zi, z1));
-            lpr[OS] = bload<float>(rs(bLp, ol), lo_b);
-            lsr[OS] = bload<float>(rs(bLs, ol), lo_b);
+            const pair_t<float> l = bload2<float>(rs(bL, poff(min(zi, z1))), lo_b);
+            lpr[OS] = l.x;
+            lsr[OS] = l.y;
         }
     };
 
@@ -847,14 +866,14 @@ __global__ void set_nstep_kernel(SolveDesc* descs, int i, long long nstep, long 
 
 template <typename S, bool COMP>
 __global__ void unpack_kernel(const S* __restrict__ src, int nx, int ny, int nz, long long sy,
-                              long long sz, void* __restrict__ hi, float* __restrict__ lo) {
+                              long long sz, int cs, void* __restrict__ hi, float* __restrict__ lo) {
     const long long total = (long long)nx * ny * nz;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const int x = (int)(i % nx);
         const long long r = i / nx;
         const int y = (int)(r % ny), z = (int)(r / ny);
-        const long long o = (long long)z * sz + (long long)y * sy + x;
+        const long long o = ((long long)z * sz + (long long)y * sy + x) * cs;
         const double v = src ? (double)src[i] : 0.0;
         if constexpr (COMP) {
             const float h = (float)v;
@@ -868,14 +887,14 @@ __global__ void unpack_kernel(const S* __restrict__ src, int nx, int ny, int nz,
 
 template <typename D, bool COMP>
 __global__ void pack_kernel(D* __restrict__ dst, int nx, int ny, int nz, long long sy, long long sz,
-                            const void* __restrict__ hi, const float* __restrict__ lo) {
+                            int cs, const void* __restrict__ hi, const float* __restrict__ lo) {
     const long long total = (long long)nx * ny * nz;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const int x = (int)(i % nx);
         const long long r = i / nx;
         const int y = (int)(r % ny), z = (int)(r / ny);
-        const long long o = (long long)z * sz + (long long)y * sy + x;
+        const long long o = ((long long)z * sz + (long long)y * sy + x) * cs;
         double v;
         if constexpr (COMP) v = (double)((const float*)hi)[o] + (double)lo[o];
         else v = ((const double*)hi)[o];
@@ -1033,31 +1052,31 @@ static unsigned grid_for(long long total) {
 }
 
 int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,
-                  long long sz, void* hi, float* lo, void* stream) {
+                  long long sz, int cs, void* hi, float* lo, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const unsigned g = grid_for((long long)nx * ny * nz);
     const bool comp = prec == PREC_F32C;
     if (src_dtype == 0) {
-        if (comp) hipLaunchKernelGGL((unpack_kernel<double, true>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, hi, lo);
-        else hipLaunchKernelGGL((unpack_kernel<double, false>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, hi, lo);
+        if (comp) hipLaunchKernelGGL((unpack_kernel<double, true>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, cs, hi, lo);
+        else hipLaunchKernelGGL((unpack_kernel<double, false>), dim3(g), dim3(256), 0, s, (const double*)src, nx, ny, nz, sy, sz, cs, hi, lo);
     } else {
-        if (comp) hipLaunchKernelGGL((unpack_kernel<float, true>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, hi, lo);
-        else hipLaunchKernelGGL((unpack_kernel<float, false>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, hi, lo);
+        if (comp) hipLaunchKernelGGL((unpack_kernel<float, true>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, cs, hi, lo);
+        else hipLaunchKernelGGL((unpack_kernel<float, false>), dim3(g), dim3(256), 0, s, (const float*)src, nx, ny, nz, sy, sz, cs, hi, lo);
     }
     return (int)hipGetLastError();
 }
 
 int launch_pack(int prec, int dst_dtype, void* dst, int nx, int ny, int nz, long long sy,
-                long long sz, const void* hi, const float* lo, void* stream) {
+                long long sz, int cs, const void* hi, const float* lo, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const unsigned g = grid_for((long long)nx * ny * nz);
     const bool comp = prec == PREC_F32C;
     if (dst_dtype == 0) {
-        if (comp) hipLaunchKernelGGL((pack_kernel<double, true>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, hi, lo);
-        else hipLaunchKernelGGL((pack_kernel<double, false>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, hi, lo);
+        if (comp) hipLaunchKernelGGL((pack_kernel<double, true>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, cs, hi, lo);
+        else hipLaunchKernelGGL((pack_kernel<double, false>), dim3(g), dim3(256), 0, s, (double*)dst, nx, ny, nz, sy, sz, cs, hi, lo);
     } else {
-        if (comp) hipLaunchKernelGGL((pack_kernel<float, true>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
-        else hipLaunchKernelGGL((pack_kernel<float, false>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, hi, lo);
+        if (comp) hipLaunchKernelGGL((pack_kernel<float, true>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, cs, hi, lo);
+        else hipLaunchKernelGGL((pack_kernel<float, false>), dim3(g), dim3(256), 0, s, (float*)dst, nx, ny, nz, sy, sz, cs, hi, lo);
     }
     return (int)hipGetLastError();
 }

@@ -85,9 +85,14 @@ int scheme_of(uint32_t flags) {
     return SCHEME_STEP;
 }
 
-// Device fields of a solve, by index: 0, 1 Y_phi (ping-pong by step parity),
-// 2, 3 Y_psi, 4..6 G1..G3 (stage-pair and per-stage schemes), 7, 8 the FP32
-// low parts of phi and psi (FP32c).
+// Device state of a solve, as views (index into Solve::f): 0, 1 Y_phi
+// (ping-pong by step parity), 2, 3 Y_psi, 4..6 G1..G3, 7, 8 the FP32 low
+// parts of phi and psi (FP32c).
+//  - whole-step solves keep the state paired (cs = 2): one field per parity
+//    holds (phi, psi) per cell, so views 2, 3 are views 0, 1 plus one element,
+//    and FP32c adds one paired field for the low parts (views 7, 8); no G;
+//  - stage-pair and per-stage solves keep one field per view (cs = 1),
+//    G1..G3 included.
 bool field_used(int k, int precision, int scheme) {
     if (k >= 4 && k <= 6) return scheme != SCHEME_STEP;
     if (k >= 7) return precision == HB_F32C;
@@ -97,10 +102,12 @@ bool field_used(int k, int precision, int scheme) {
 struct Layout {
     int nx, ny, nz;
     size_t esz;             // bytes per element
-    long long sy, sz;       // row / plane pitch (elements)
-    long long origin_off;   // elements from field start to interior (0,0,0)
-    long long field_elems;  // elements per field (multiple of 256 bytes)
-    int nfields;            // fields allocated (field_used): 4 or 6 whole-step, 7 or 9 otherwise
+    int cs;                 // elements per cell (2: paired state, 1: separate fields)
+    long long sy, sz;       // row / plane pitch (cells)
+    long long origin_off;   // cells from field start to interior (0,0,0)
+    long long field_cells;  // cells per field (a multiple of 256 bytes)
+    int nfields;            // fields allocated: 2 or 3 paired, 7 or 9 separate
+    size_t cell_bytes() const { return esz * (size_t)cs; }
 };
 
 Layout plan_layout(const hb_config& c, int scheme) {
@@ -109,22 +116,26 @@ Layout plan_layout(const hb_config& c, int scheme) {
     L.ny = c.n[1];
     L.nz = c.n[2];
     L.esz = c.precision == HB_F32C ? 4 : 8;
-    const long long line = 128 / (long long)L.esz;  // elements per 128-byte line
+    L.cs = scheme == SCHEME_STEP ? 2 : 1;
+    const long long line = 128 / (long long)L.cell_bytes();  // cells per 128-byte line
     L.sy = round_up((long long)L.nx + 4, line);
     L.sz = L.sy * ((long long)L.ny + 4);
     // cell (-2, y, z) starts a 128-byte line: a tile region that starts two
-    // cells before a multiple of the tile width (32 for the whole-step
-    // kernel) reads whole lines
+    // cells before a multiple of the tile width reads whole lines
     L.origin_off = 2 * L.sz + 2 * L.sy + 2;
     const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
                            L.nx + 2;
-    L.field_elems = round_up(last, 256 / (long long)L.esz);
-    L.nfields = 0;
-    for (int k = 0; k < 9; ++k) L.nfields += field_used(k, c.precision, scheme) ? 1 : 0;
+    L.field_cells = round_up(last, 256 / (long long)L.cell_bytes());
+    if (L.cs == 2) {
+        L.nfields = c.precision == HB_F32C ? 3 : 2;
+    } else {
+        L.nfields = 0;
+        for (int k = 0; k < 9; ++k) L.nfields += field_used(k, c.precision, scheme) ? 1 : 0;
+    }
     return L;
 }
 
-size_t field_bytes(const Layout& L) { return (size_t)L.field_elems * L.esz; }
+size_t field_bytes(const Layout& L) { return (size_t)L.field_cells * L.cell_bytes(); }
 
 int validate(const hb_config* c) {
     if (!c) return fail(HB_E_ARG, "config is NULL");
@@ -140,12 +151,12 @@ int validate(const hb_config* c) {
     if (!(c->dt > 0) || !std::isfinite(c->dt)) return fail(HB_E_ARG, "dt must be > 0");
     if (c->inv_L2 < 0) return fail(HB_E_ARG, "inv_L2 must be >= 0");
     if (c->precision != HB_F64 && c->precision != HB_F32C) return fail(HB_E_ARG, "bad precision");
-    {
+    if (scheme_of(c->flags) == SCHEME_STEP) {
         // the whole-step kernel addresses a plane with 32-bit byte offsets
         const Layout L = plan_layout(*c, SCHEME_STEP);
-        if ((double)L.sz * L.esz >= 2147483648.0)
-            return fail(HB_E_ARG, "an x-y plane (%lld x %lld padded cells) must be under 2 GiB",
-                        L.sy, (long long)c->n[1] + 4);
+        if ((double)L.sz * (double)L.cell_bytes() >= 2147483648.0)
+            return fail(HB_E_ARG, "an x-y plane (%lld x %lld padded cells of %zu bytes) must be under 2 GiB",
+                        L.sy, (long long)c->n[1] + 4, L.cell_bytes());
     }
     if (!(c->flags & HB_ALLOW_UNSTABLE)) {
         // RK4 is stable on the imaginary axis up to |z| = 2 sqrt(2); -Lap_h has
@@ -213,10 +224,21 @@ int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
     }
     // zero everything once: the halo stays zero for the life of the solve
     HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
-    int slot = 0;
-    for (int k = 0; k < 9; ++k)
-        if (field_used(k, c.precision, scheme))
-            s.f[k] = s.mem + fb * (size_t)slot++ + (size_t)s.L.origin_off * s.L.esz;
+    const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
+    if (s.L.cs == 2) {
+        for (int par = 0; par < 2; ++par) {
+            s.f[par] = s.mem + fb * (size_t)par + org;
+            s.f[2 + par] = (char*)s.f[par] + s.L.esz;
+        }
+        if (c.precision == HB_F32C) {
+            s.f[7] = s.mem + fb * 2 + org;
+            s.f[8] = (char*)s.f[7] + sizeof(float);
+        }
+    } else {
+        int slot = 0;
+        for (int k = 0; k < 9; ++k)
+            if (field_used(k, c.precision, scheme)) s.f[k] = s.mem + fb * (size_t)slot++ + org;
+    }
     return HB_OK;
 }
 
@@ -278,6 +300,7 @@ SolveDesc make_desc(const Solve& s) {
     d.ctab = s.ctab;
     d.sy = s.L.sy;
     d.sz = s.L.sz;
+    d.cs = s.L.cs;
     d.nx = s.L.nx;
     d.ny = s.L.ny;
     d.nz = s.L.nz;
@@ -321,8 +344,8 @@ int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const vo
             }
             dsrc = staged;
         }
-        int r = launch_unpack(s.prec(), dtype, dsrc, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, hi[k],
-                              lo[k], stream);
+        int r = launch_unpack(s.prec(), dtype, dsrc, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, s.L.cs,
+                              hi[k], lo[k], stream);
         if (staged) {
             // the host copy and the unpack must finish before the staging buffer goes
             hipError_t e = hipStreamSynchronize(stream);
@@ -347,13 +370,13 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
         if (!dst[k]) continue;
         if (mem == HB_DEVICE) {
             HB_TRY(from_hip(launch_pack(s.prec(), dtype, dst[k], s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz,
-                                        hi[k], lo[k], stream),
+                                        s.L.cs, hi[k], lo[k], stream),
                             "pack"));
         } else {
             void* staged = nullptr;
             HB_TRY(dev_alloc(&staged, bytes, "staging buffer"));
-            int r = launch_pack(s.prec(), dtype, staged, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, hi[k],
-                                lo[k], stream);
+            int r = launch_pack(s.prec(), dtype, staged, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz,
+                                s.L.cs, hi[k], lo[k], stream);
             hipError_t e = r ? (hipError_t)r : hipMemcpyAsync(dst[k], staged, bytes,
                                                               hipMemcpyDeviceToHost, stream);
             hipError_t e2 = hipStreamSynchronize(stream);
@@ -860,17 +883,29 @@ struct Snapshot {
     }
 };
 
+// the allocated fields that hold the state of step parity `par` (paired:
+// the state field and, FP32c, the low parts; separate: phi, psi and the low
+// parts), as field start addresses
+std::vector<char*> state_fields(const Solve& s, int par) {
+    const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
+    std::vector<int> views = {par};
+    if (s.L.cs == 1) views.push_back(2 + par);
+    if (s.prec() == HB_F32C) {
+        views.push_back(7);
+        if (s.L.cs == 1) views.push_back(8);
+    }
+    std::vector<char*> out;
+    for (int v : views) out.push_back((char*)s.f[v] - org);
+    return out;
+}
+
 int snapshot_take(Group& g, Snapshot& snap, hipStream_t stream) {
     for (Solve* s : g.members) {
         const size_t fb = field_bytes(s->L);
-        const int par = (int)(s->nstep & 1);
-        const int idx[4] = {0 + par, 2 + par, 7, 8};
-        const int nf = s->prec() == HB_F32C ? 4 : 2;
-        for (int k = 0; k < nf; ++k) {
+        for (char* base : state_fields(*s, (int)(s->nstep & 1))) {
             void* b = nullptr;
             HB_TRY(dev_alloc(&b, fb, "autotune snapshot"));
             snap.bufs.push_back(b);
-            char* base = (char*)s->f[idx[k]] - (size_t)s->L.origin_off * s->L.esz;
             HIP_TRY(hipMemcpyAsync(b, base, fb, hipMemcpyDeviceToDevice, stream));
         }
     }
@@ -884,13 +919,8 @@ int snapshot_restore(Group& g, Snapshot& snap, const std::vector<long long>& nst
         s->nstep = nsteps[m];
         s->target = nsteps[m];
         const size_t fb = field_bytes(s->L);
-        const int par = (int)(s->nstep & 1);
-        const int idx[4] = {0 + par, 2 + par, 7, 8};
-        const int nf = s->prec() == HB_F32C ? 4 : 2;
-        for (int k = 0; k < nf; ++k) {
-            char* base = (char*)s->f[idx[k]] - (size_t)s->L.origin_off * s->L.esz;
+        for (char* base : state_fields(*s, (int)(s->nstep & 1)))
             HIP_TRY(hipMemcpyAsync(base, snap.bufs[i++], fb, hipMemcpyDeviceToDevice, stream));
-        }
     }
     HIP_TRY(hipStreamSynchronize(stream));
     return HB_OK;

@@ -1,6 +1,7 @@
 """Parity at the largest x-y planes the library accepts.  The whole-step
-kernel addresses a plane with 32-bit byte offsets, so a padded plane must stay
-under 2 GiB; the largest square one-plane grids are found from hb_footprint
+kernel addresses a plane with 32-bit byte offsets, so a padded plane of paired
+cells (16 B FP64, 8 B FP32c) must stay under 2 GiB; the largest square
+one-plane grids are found from hb_footprint
 (host-only) and the next size up must be rejected.  Two steps on the GPU, then
 sampled nodes (corners, edges, the far end of the plane where the offsets are
 largest, random nodes) against the oracle run on a window around each node
@@ -31,12 +32,12 @@ def largest_square_plane(hb, prec):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["f64", "f32c"])
 def test_largest_plane_vs_oracle_windows(hb, oracle_mod, prec, tol):
     n = largest_square_plane(hb, prec)
-    esz = 8 if prec == 0 else 4
-    line = 128 // esz
+    cell = 16 if prec == 0 else 8  # the paired state (phi, psi) of a cell
+    line = 128 // cell
     pitch = (n + 4 + line - 1) // line * line
-    assert pitch * (n + 4) * esz < 2 ** 31 <= ((n + 5 + line - 1) // line * line) * (n + 5) * esz
+    assert pitch * (n + 4) * cell < 2 ** 31 <= ((n + 5 + line - 1) // line * line) * (n + 5) * cell
     print(f"largest accepted plane, precision {prec}: {n} x {n} "
-          f"({pitch * (n + 4) * esz} bytes padded)", flush=True)
+          f"({pitch * (n + 4) * cell} bytes padded)", flush=True)
     steps = 2
     w = si.wide_plane(n, n, steps=steps)
     p0 = w.phi0()
