@@ -30,8 +30,10 @@ diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restri
     const long long sy = d->sy, sz = d->sz, cs = d->cs;  // cs elements per cell
     const void* P = d->y_phi[par];
     const void* S = d->y_psi[par];
-    const float* LP = d->lo_phi;
-    const float* LS = d->lo_psi;
+    // FP32c low parts: in the whole-step state slot (phi hi, psi hi, phi lo,
+    // psi lo) two elements after the high parts, else their own fields
+    const float* LP = d->cs == 4 ? (const float*)P + 2 : d->lo_phi;
+    const float* LS = d->cs == 4 ? (const float*)S + 2 : d->lo_psi;
     const double w0 = d->w0, mu2 = d->mu2, lam = d->lambda;
     double acc[DIAG_COUNT];
     for (int k = 0; k < DIAG_COUNT; ++k) acc[k] = 0.0;

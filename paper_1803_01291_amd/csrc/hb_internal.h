@@ -3,11 +3,12 @@
 // Field layout in HBM (one allocation per solve, all fields alike):
 //   cell (x, y, z), x in [-2, nx+2), y in [-2, ny+2), z in [-2, nz+2), holds
 //   its value at element cs * (z*sz + y*sy + x) from the field's origin (the
-//   interior point (0, 0, 0)).  cs = 1 for separate fields; cs = 2 for the
-//   paired state of whole-step solves, where one field holds (phi, psi) per
-//   cell (FP32c: the high parts in one paired field, the low parts in
-//   another), so a cell's state moves in one 16-byte (8-byte) access; the psi
-//   view of a paired field is its phi view plus one element.  The row pitch
+//   interior point (0, 0, 0)).  cs = 1 for separate fields.  Whole-step
+//   solves keep a cell's state in one 16-byte slot, one field per step
+//   parity: (phi, psi) in FP64 (cs = 2) or (phi hi, psi hi, phi lo, psi lo)
+//   in FP32c (cs = 4), so a cell's state moves in one 16-byte access; the
+//   psi view is the phi view plus one element, the low parts follow at two
+//   and three elements.  The row pitch
 //   sy is nx+4 rounded up to a 128-byte multiple of cells and cell (0, y, z)
 //   starts a 128-byte line.  The 2-cell halo (the zero boundary condition) is
 //   zeroed once at creation and never written afterwards.
@@ -23,14 +24,14 @@ enum : int { PREC_F64 = 0, PREC_F32C = 1 };
 // One solve as the stage kernels see it (device resident, 128-byte aligned).
 struct SolveDesc {
     void* y_phi[2];      // state phi (FP64) or its FP32 high part, ping-pong by step parity
-    void* y_psi[2];      // state psi, same (paired: y_phi[p] + one element)
+    void* y_psi[2];      // state psi, same (whole-step slot: y_phi[p] + one element)
     void* g[3];          // psi-forcing of stages 1..3 (G1, G2, G3; separate fields only)
-    float* lo_phi;       // FP32c: low parts of the compensated state (updated in place)
-    float* lo_psi;       // (paired: lo_phi + one element)
+    float* lo_phi;       // FP32c, separate fields: low parts of the compensated state
+    float* lo_psi;       // (updated in place); whole-step solves keep them in the state slot
     const double* ctab;  // c(t) per stage: ctab[4 n + s], s = 0..3
     long long sy, sz;    // row and plane pitch in cells
     int nx, ny, nz, prec;
-    int cs;              // elements per cell: 1 (separate fields) or 2 (paired state)
+    int cs;              // elements per cell: 1 (separate fields), 2 or 4 (whole-step state slot)
     int pad0_;
     double w0;           // -5/2 (1/hx^2 + 1/hy^2 + 1/hz^2)
     double w1[3];        // 4/3 / h_d^2

@@ -111,6 +111,17 @@ __device__ __forceinline__ pair_t<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t o
         return __builtin_bit_cast(pair_t<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+// An FP32c cell (phi hi, psi hi, phi lo, psi lo) in one 16-byte access.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, uint32_t off, f32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ void bstore2(__amdgpu_buffer_rsrc_t r, uint32_t off, T a, T b) {
     pair_t<T> v;
@@ -591,13 +602,13 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     if (n >= d->target) return;  // uniform over the block
     const int par = (int)(n & 1);
 
-    // paired state: (phi, psi) of a cell side by side (FP32c: the high parts;
-    // the low parts in a second paired field)
+    // the state of a cell in one 16-byte slot: (phi, psi) in FP64, or
+    // (phi hi, psi hi, phi lo, psi lo) in FP32c, ping-pong by step parity
     const T* __restrict__ Y = (const T*)d->y_phi[par];
     T* __restrict__ O = (T*)d->y_phi[par ^ 1];
     const long long sy = d->sy, sz = d->sz;
     const int nx = d->nx, ny = d->ny, nz = d->nz;
-    constexpr int CB = 2 * sizeof(T);  // bytes per cell
+    constexpr int CB = 16;  // bytes per cell
 
     const T c1 = (T)ldg(d->ctab, 4 * n + 0, true), c2 = (T)ldg(d->ctab, 4 * n + 1, true);
     const T c3 = (T)ldg(d->ctab, 4 * n + 2, true), c4 = (T)ldg(d->ctab, 4 * n + 3, true);
@@ -628,7 +639,6 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const int pbytes = (int)(sz * (long long)CB);
     const long long cb = (2 * sy + 2) * (long long)CB;
     const unsigned long long bY = (unsigned long long)Y - cb, bO = (unsigned long long)O - cb;
-    const unsigned long long bL = (unsigned long long)d->lo_phi - cb;
     auto poff = [&](int p) -> unsigned long long { return (unsigned long long)((long long)p * pbytes); };
     auto rs = [&](unsigned long long b, unsigned long long off) { return plane_rsrc(b + off, pbytes); };
     auto clampz = [&](int p) { return min(max(p, -2), nz + 1); };
@@ -652,7 +662,6 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     // threads without an outer-ring column load the plane's corner cell (a
     // halo zero), so every thread issues the same loads
     const uint32_t outer_b = has_outer ? col_bytes(tl.x0 - 4 + ox, tl.y0 - 4 + oy) : 0u;
-    const uint32_t lo_b = own_st ? col_b : 0u;           // FP32c low parts
     const uint32_t out_b = own_st ? col_b : BUF_SKIP;    // output column or none
 
     const int z0 = tl.z0, z1 = tl.z1;
@@ -668,24 +677,31 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     T a3q[6], a4q[6];      // own-column S_phi,3 and S_phi,4
     T g1r[6], g2r[6];      // own-column G1, G2
     T opr[3], osr[3];      // outer-ring Y, by plane mod 3
-    float lpr[3], lsr[3];  // FP32c low parts, by output plane mod 3
+    float lqp[6], lqs[6];  // FP32c low parts of the own column, like qp, qs
     for (int k = 0; k < 6; ++k) {
         qp[k] = qs[k] = a3q[k] = a4q[k] = g1r[k] = g2r[k] = T(0);
+        lqp[k] = lqs[k] = 0.f;
     }
-    for (int k = 0; k < 3; ++k) {
-        opr[k] = osr[k] = T(0);
-        lpr[k] = lsr[k] = 0.f;
-    }
+    for (int k = 0; k < 3; ++k) opr[k] = osr[k] = T(0);
+    // own column of plane p into ring slot k (FP32c: the low parts too)
+    auto ld_own_slot = [&](int k, int p) {
+        if constexpr (COMP) {
+            const f32x4 v = bload4(rs(bY, poff(p)), col_b);
+            qp[k] = v.x;
+            qs[k] = v.y;
+            lqp[k] = v.z;
+            lqs[k] = v.w;
+        } else {
+            const pair_t<T> v = bload2<T>(rs(bY, poff(p)), col_b);
+            qp[k] = v.x;
+            qs[k] = v.y;
+        }
+    };
     // prologue: own Y at planes zbase-2 .. zbase+3, outer ring at planes
     // zbase .. zbase+2, issued in the order the march issues them (own plane
     // p, then outer plane p-1), so the waits in the march's first pass are
     // those of every later pass
-    auto ld_own = [&](int k) {
-        const int p = zbase - 2 + k;
-        const pair_t<T> v = bload2<T>(rs(bY, poff(clampz(p))), col_b);
-        qp[(k + 4) % 6] = v.x;
-        qs[(k + 4) % 6] = v.y;
-    };
+    auto ld_own = [&](int k) { ld_own_slot((k + 4) % 6, clampz(zbase - 2 + k)); };
     auto ld_outer = [&](int k) {
         const int p = zbase + k;
         const pair_t<T> v = bload2<T>(rs(bY, poff(clampz(p))), outer_b);
@@ -712,8 +728,7 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         constexpr int B = PH & 1;                    // LDS double buffer
         constexpr int RS = PH % 3;                   // LDS ring slot of plane zi
         constexpr int RS2 = (PH + 1) % 3;            // ... of plane zi - 2
-        constexpr int OS = PH % 3;                   // outer / low-part slot of plane zi
-        constexpr int OS2 = (PH + 1) % 3;            // ... of plane zi - 2
+        constexpr int OS = PH % 3;                   // outer-ring slot of plane zi
         auto Q = [](int k) { return (PH + 6 + k) % 6; };  // ring slot of plane zi + k
         const int zi = zbase + it;
 
@@ -782,8 +797,8 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                 op_ = (T)u.p;
                 os_ = (T)u.s;
             } else {
-                const double pp = (double)yp + (double)lpr[OS2];
-                const double ss = (double)ys + (double)lsr[OS2];
+                const double pp = (double)yp + (double)lqp[Q(-2)];
+                const double ss = (double)ys + (double)lqs[Q(-2)];
                 const Upd u = rk4_update(pp, ss, e1, e2, g3, g4, hdd, dtd, dt6);
                 const float hp = (float)u.p, hs = (float)u.s;
                 op_ = hp;
@@ -798,9 +813,16 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             // (outside [z0, z1) no lane stores, so the base of plane z is
             // never dereferenced even where z is outside the field)
             const uint32_t ob = zout ? out_b : BUF_SKIP;
-            const unsigned long long o = poff(z);
-            bstore2<T>(rs(bO, o), ob, op_, os_);
-            if constexpr (COMP) bstore2<float>(rs(bL, o), ob, ol_p, ol_s);
+            if constexpr (COMP) {
+                f32x4 w;
+                w.x = op_;
+                w.y = os_;
+                w.z = ol_p;
+                w.w = ol_s;
+                bstore4(rs(bO, poff(z)), ob, w);
+            } else {
+                bstore2<T>(rs(bO, poff(z)), ob, op_, os_);
+            }
         }
 
         // ---- loads for later planes, into the slots this plane freed ----
@@ -808,20 +830,12 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         // clamped and the value is never used)
         // own plane zi+4 into the slot of plane zi-2 (last used just above);
         // zi+4 >= z0+2 >= 2, and planes past nz+1 are never needed
-        const pair_t<T> v4 = bload2<T>(rs(bY, poff(min(zi + 4, zlast))), col_b);
-        qp[Q(4)] = v4.x;
-        qs[Q(4)] = v4.y;
-        // outer plane zi+3 into the slot of plane zi (used before the barrier)
+        ld_own_slot(Q(4), min(zi + 4, zlast));
+        // outer plane zi+3 into the slot of plane zi (used before the barrier);
+        // the stencil needs only (phi, psi) (FP32c: the high parts)
         const pair_t<T> v3 = bload2<T>(rs(bY, poff(min(zi + 3, z1 + 1))), outer_b);
         opr[OS] = v3.x;
         osr[OS] = v3.y;
-        if constexpr (COMP) {
-            // low parts of output plane zi (updated two planes from now);
-            // the slot held output plane zi-3's, used one plane ago
-            const pair_t<float> l = bload2<float>(rs(bL, poff(min(zi, z1))), lo_b);
-            lpr[OS] = l.x;
-            lsr[OS] = l.y;
-        }
     };
 
     using I0 = std::integral_constant<int, 0>;

@@ -87,12 +87,13 @@ int scheme_of(uint32_t flags) {
 
 // Device state of a solve, as views (index into Solve::f): 0, 1 Y_phi
 // (ping-pong by step parity), 2, 3 Y_psi, 4..6 G1..G3, 7, 8 the FP32 low
-// parts of phi and psi (FP32c).
-//  - whole-step solves keep the state paired (cs = 2): one field per parity
-//    holds (phi, psi) per cell, so views 2, 3 are views 0, 1 plus one element,
-//    and FP32c adds one paired field for the low parts (views 7, 8); no G;
+// parts of phi and psi (FP32c; see lo_view).
+//  - whole-step solves keep a cell's state in one 16-byte slot, one field per
+//    parity: (phi, psi) in FP64 (cs = 2), (phi hi, psi hi, phi lo, psi lo) in
+//    FP32c (cs = 4); views 2, 3 are views 0, 1 plus one element, the low
+//    parts views 0, 1 plus two and three elements; no G;
 //  - stage-pair and per-stage solves keep one field per view (cs = 1),
-//    G1..G3 included.
+//    G1..G3 included, and one low-part field per quantity (updated in place).
 bool field_used(int k, int precision, int scheme) {
     if (k >= 4 && k <= 6) return scheme != SCHEME_STEP;
     if (k >= 7) return precision == HB_F32C;
@@ -102,11 +103,11 @@ bool field_used(int k, int precision, int scheme) {
 struct Layout {
     int nx, ny, nz;
     size_t esz;             // bytes per element
-    int cs;                 // elements per cell (2: paired state, 1: separate fields)
+    int cs;                 // elements per cell (2 or 4: whole-step state slot, 1: separate fields)
     long long sy, sz;       // row / plane pitch (cells)
     long long origin_off;   // cells from field start to interior (0,0,0)
     long long field_cells;  // cells per field (a multiple of 256 bytes)
-    int nfields;            // fields allocated: 2 or 3 paired, 7 or 9 separate
+    int nfields;            // fields allocated: 2 whole-step, 7 or 9 separate
     size_t cell_bytes() const { return esz * (size_t)cs; }
 };
 
@@ -116,7 +117,7 @@ Layout plan_layout(const hb_config& c, int scheme) {
     L.ny = c.n[1];
     L.nz = c.n[2];
     L.esz = c.precision == HB_F32C ? 4 : 8;
-    L.cs = scheme == SCHEME_STEP ? 2 : 1;
+    L.cs = scheme == SCHEME_STEP ? (c.precision == HB_F32C ? 4 : 2) : 1;
     const long long line = 128 / (long long)L.cell_bytes();  // cells per 128-byte line
     L.sy = round_up((long long)L.nx + 4, line);
     L.sz = L.sy * ((long long)L.ny + 4);
@@ -127,8 +128,8 @@ Layout plan_layout(const hb_config& c, int scheme) {
     const long long last = L.origin_off + ((long long)L.nz + 1) * L.sz + ((long long)L.ny + 1) * L.sy +
                            L.nx + 2;
     L.field_cells = round_up(last, 256 / (long long)L.cell_bytes());
-    if (L.cs == 2) {
-        L.nfields = c.precision == HB_F32C ? 3 : 2;
+    if (L.cs > 1) {
+        L.nfields = 2;
     } else {
         L.nfields = 0;
         for (int k = 0; k < 9; ++k) L.nfields += field_used(k, c.precision, scheme) ? 1 : 0;
@@ -181,8 +182,8 @@ struct Solve {
     hb_config cfg{};
     Layout L{};
     char* mem = nullptr;          // all fields, one allocation
-    void* f[9] = {};              // origins: phi0, phi1, psi0, psi1, G1, G2, G3, lo_phi, lo_psi
-                                  // (NULL where not allocated)
+    void* f[9] = {};              // views: phi0, phi1, psi0, psi1, G1, G2, G3, lo_phi, lo_psi
+                                  // (NULL where not allocated; lo_view gives the low parts)
     double* ctab = nullptr;       // device c(t) table, 4 per step
     long long ctab_steps = 0;
     long long nstep = 0;          // host mirror of the device counter
@@ -195,6 +196,12 @@ struct Solve {
         if (ctab) (void)hipFree(ctab);
     }
     int prec() const { return cfg.precision; }
+    // FP32c low parts of phi (k = 0) or psi (k = 1) of the state at step
+    // parity par: inside the whole-step state slot, else the in-place field
+    float* lo_view(int k, int par) const {
+        if (L.cs == 4) return (float*)f[par] + 2 + k;
+        return (float*)f[7 + k];
+    }
 };
 
 // steps the coefficient table holds when it must cover `need` steps
@@ -226,14 +233,10 @@ int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
     // zero everything once: the halo stays zero for the life of the solve
     HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
     const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
-    if (s.L.cs == 2) {
+    if (s.L.cs > 1) {
         for (int par = 0; par < 2; ++par) {
             s.f[par] = s.mem + fb * (size_t)par + org;
             s.f[2 + par] = (char*)s.f[par] + s.L.esz;
-        }
-        if (c.precision == HB_F32C) {
-            s.f[7] = s.mem + fb * 2 + org;
-            s.f[8] = (char*)s.f[7] + sizeof(float);
         }
     } else {
         int slot = 0;
@@ -296,7 +299,7 @@ SolveDesc make_desc(const Solve& s) {
     d.g[0] = s.f[4];
     d.g[1] = s.f[5];
     d.g[2] = s.f[6];
-    d.lo_phi = (float*)s.f[7];
+    d.lo_phi = (float*)s.f[7];  // separate fields only (the whole-step slot holds its own)
     d.lo_psi = (float*)s.f[8];
     d.ctab = s.ctab;
     d.sy = s.L.sy;
@@ -332,7 +335,7 @@ int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const vo
     const size_t bytes = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
     const void* src[2] = {phi, psi};
     void* hi[2] = {s.f[slot_phi], s.f[slot_psi]};
-    float* lo[2] = {(float*)s.f[7], (float*)s.f[8]};
+    float* lo[2] = {s.lo_view(0, slot_phi & 1), s.lo_view(1, slot_phi & 1)};
     for (int k = 0; k < 2; ++k) {
         const void* dsrc = src[k];
         void* staged = nullptr;
@@ -366,7 +369,7 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
     const size_t bytes = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
     void* dst[2] = {phi, psi};
     const void* hi[2] = {s.f[0 + par], s.f[2 + par]};
-    const float* lo[2] = {(const float*)s.f[7], (const float*)s.f[8]};
+    const float* lo[2] = {s.lo_view(0, par), s.lo_view(1, par)};
     for (int k = 0; k < 2; ++k) {
         if (!dst[k]) continue;
         if (mem == HB_DEVICE) {
@@ -890,10 +893,12 @@ struct Snapshot {
 std::vector<char*> state_fields(const Solve& s, int par) {
     const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
     std::vector<int> views = {par};
-    if (s.L.cs == 1) views.push_back(2 + par);
-    if (s.prec() == HB_F32C) {
-        views.push_back(7);
-        if (s.L.cs == 1) views.push_back(8);
+    if (s.L.cs == 1) {
+        views.push_back(2 + par);
+        if (s.prec() == HB_F32C) {
+            views.push_back(7);
+            views.push_back(8);
+        }
     }
     std::vector<char*> out;
     for (int v : views) out.push_back((char*)s.f[v] - org);

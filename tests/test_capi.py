@@ -39,7 +39,8 @@ def test_footprint_is_host_only(lib):
     # whole-step scheme: the paired state (phi, psi) at two parities, 16 B per cell
     assert 2 * 256 ** 3 * 16 < fp < 2 * 280 ** 3 * 16
     c32 = hb.make_config((256, 256, 256), (-16,) * 3, (16,) * 3, 2.0, 1.0, 0.005, precision=hb.HB_F32C)
-    assert 3 * 256 ** 3 * 8 < hb.hb_footprint(c32) < 3 * 280 ** 3 * 8   # + paired low parts
+    # FP32c: (phi hi, psi hi, phi lo, psi lo) at two parities, 16 B per cell
+    assert 2 * 256 ** 3 * 16 < hb.hb_footprint(c32) < 2 * 280 ** 3 * 16
     # the stage-pair and per-stage schemes keep 7 separate fields (G1..G3 too);
     # their rows round to 16 instead of 8 cells, hence the band
     for flags in (hb.HB_PAIRWISE, hb.HB_STAGEWISE):
@@ -52,15 +53,16 @@ def test_footprint_is_host_only(lib):
 
 def test_plane_size_limit_is_rejected(lib):
     """The whole-step kernel addresses a plane with 32-bit byte offsets: an x-y
-    plane of 2 GiB or more (paired cells: 16 B FP64, 8 B FP32c) is rejected
-    before anything is allocated (footprint 0, message)."""
+    plane of 2 GiB or more (16-byte cells, FP64 and FP32c) is rejected before
+    anything is allocated (footprint 0, message)."""
     from paper_1803_01291_amd import hb
-    ok = hb.make_config((11600, 11600, 1), (-1,) * 3, (1,) * 3, 1.0, 1.0, 1e-9,
-                        flags=hb.HB_ALLOW_UNSTABLE, precision=hb.HB_F32C)
-    assert hb.hb_footprint(ok) > 0          # 11616 x 11604 x 8 B = 1.0 GiB per plane
+    for prec in (hb.HB_F64, hb.HB_F32C):
+        ok = hb.make_config((11500, 11500, 1), (-1,) * 3, (1,) * 3, 1.0, 1.0, 1e-9,
+                            flags=hb.HB_ALLOW_UNSTABLE, precision=prec)
+        assert hb.hb_footprint(ok) > 0      # 11504 x 11504 x 16 B = 1.97 GiB per plane
     big = hb.make_config((11600, 11600, 1), (-1,) * 3, (1,) * 3, 1.0, 1.0, 1e-9,
                          flags=hb.HB_ALLOW_UNSTABLE)
-    assert hb.hb_footprint(big) == 0        # FP64: 2 GiB per plane
+    assert hb.hb_footprint(big) == 0        # 11608 x 11604 x 16 B = 2.007 GiB per plane
     assert "2 GiB" in hb.hb_last_error()
 
 

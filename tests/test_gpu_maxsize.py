@@ -1,6 +1,6 @@
 """Parity at the largest x-y planes the library accepts.  The whole-step
-kernel addresses a plane with 32-bit byte offsets, so a padded plane of paired
-cells (16 B FP64, 8 B FP32c) must stay under 2 GiB; the largest square
+kernel addresses a plane with 32-bit byte offsets, so a padded plane of
+16-byte cells must stay under 2 GiB; the largest square
 one-plane grids are found from hb_footprint
 (host-only) and the next size up must be rejected.  Two steps on the GPU, then
 sampled nodes (corners, edges, the far end of the plane where the offsets are
@@ -32,7 +32,7 @@ def largest_square_plane(hb, prec):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["f64", "f32c"])
 def test_largest_plane_vs_oracle_windows(hb, oracle_mod, prec, tol):
     n = largest_square_plane(hb, prec)
-    cell = 16 if prec == 0 else 8  # the paired state (phi, psi) of a cell
+    cell = 16  # a cell's state slot: (phi, psi) FP64 or (phi hi, psi hi, phi lo, psi lo) FP32c
     line = 128 // cell
     pitch = (n + 4 + line - 1) // line * line
     assert pitch * (n + 4) * cell < 2 ** 31 <= ((n + 5 + line - 1) // line * line) * (n + 5) * cell
