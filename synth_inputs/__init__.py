@@ -21,6 +21,8 @@ synthetic workloads derived from it:
   (maximum ``A`` at the centre).
 * ``paper_bump``     -- the paper's section 3 bump
   ``exp(1/R^2 - 1/(R^2 - |x-C|^2))`` inside ``|x-C| < R``, else 0.
+* ``example6_data``  -- the non-radial, sign-changing data of section 3,
+  Example 6, on the unit box.
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ __all__ = [
     "axis_nodes", "grid_mesh", "gaussian_sum", "cinf_bump", "paper_bump",
     "radial_gaussian", "Workload", "config1", "config2", "config3",
     "batch_config", "serving_trace", "ServeRequest", "small_case", "wide_plane",
-    "slab_config",
+    "slab_config", "example6_data",
 ]
 
 
@@ -105,6 +107,17 @@ def paper_bump(n, lo, hi, C, R: float) -> np.ndarray:
     m = r2 < R * R
     out[m] = np.exp(1.0 / (R * R) - 1.0 / (R * R - r2[m]))
     return out
+
+
+def example6_data(n: int, C, C2, R: float, a0: float, a1: float):
+    """Section 3, Example 6, on the unit box with ``n`` cells per axis:
+    ``phi0 = a0 B(x; C, R) B(x; C2, R) sin(2 pi x_1)`` (``x_1`` the first
+    coordinate) and ``phi1 = a1 B(x; C, R)``."""
+    nn, lo, hi = (n, n, n), (0.0,) * 3, (1.0,) * 3
+    _, _, X = grid_mesh(nn, lo, hi)
+    b1 = paper_bump(nn, lo, hi, C, R)
+    b2 = paper_bump(nn, lo, hi, C2, R)
+    return a0 * b1 * b2 * np.sin(2.0 * np.pi * X), a1 * b1
 
 
 @dataclasses.dataclass

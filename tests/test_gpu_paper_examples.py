@@ -1,7 +1,9 @@
-"""The paper's section 3 examples on the GPU path at reduced resolution.
+"""The paper's section 3 examples on the GPU path at reduced resolution
+(Examples 3, 4, 5 and 6).
 
 Unit box [0,1]^3 (cell-centred), L = 5 (inv_L2 = 1/25), the paper's bump
-B(x; C, R) = exp(1/R^2 - 1/(R^2 - |x-C|^2)) with C the box centre.  Each run
+B(x; C, R) = exp(1/R^2 - 1/(R^2 - |x-C|^2)) with C the box centre (Example
+6 multiplies two bumps and a sine, and is not radial).  Each run
 is checked against the oracle at the same resolution (same discrete
 problem) and against the facts the paper prints (tests/golden/
 paper_facts.json).
@@ -95,3 +97,45 @@ def test_example4_plateau_and_P(hb):
     ratios = [P[i + 1] / P[i] for i in range(4, len(P) - 1)]
     assert all(r < 0.2 for r in ratios), ratios
     assert P[-1] < 1e-5 * P[0]
+
+
+def example6_case(n, dt):
+    f = FACTS["example6_positive_limit"]
+    p0, p1 = si.example6_data(n, f["bump_centre"], f["second_centre"], f["bump_radius"],
+                              f["phi0_amp"], f["phi1_amp"])
+    nn, lo, hi = (n, n, n), (0.0,) * 3, (1.0,) * 3
+    return si.Workload(f"paper_example6_{n}", nn, lo, hi, mu2=f["mu2"], lam=f["lambda"], dt=dt,
+                       steps=0, inv_L2=1.0 / f["L"] ** 2, phi0=lambda: p0, phi1=lambda: p1)
+
+
+def test_example6_parity(hb, oracle_mod):
+    """Example 6's non-radial, sign-changing data: GPU against the oracle at
+    48^3 over t in [0, 1] (500 steps), every node."""
+    w = example6_case(48, 2e-3)
+    (phi, psi, _), = run_segments(hb, w, [500])
+    err = oracle.rel_maxnorm(phi, psi, *oracle.solve_workload(w, nsteps=500))
+    print(f"Example 6 (48^3 x 500): relative max-norm error {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_example6_positive_limit(hb):
+    """At 96^3: the negative lobe of phi0 is gone from t = 1 on (what stays
+    below zero is far-field rounding dust), and at t = 4 the positive region
+    sits at sqrt(9/2), printed as 2.12."""
+    f = FACTS["example6_positive_limit"]
+    dt, n = 2e-3, 96
+    w = example6_case(n, dt)
+    k = int(round(1.0 / dt))
+    states = run_segments(hb, w, [k] * int(round(f["t"])))
+    for i, (phi, _, d) in enumerate(states):
+        print(f"Example 6 (96^3) t={i + 1}: min {phi.min():.3e}, max {phi.max():.5f}")
+        assert phi.min() > -1e-4 * phi.max()
+        assert d["nonfinite"] == 0
+    phi = states[-1][0]
+    c = n // 2
+    centre = phi[c - 1:c + 1, c - 1:c + 1, c - 1:c + 1].mean()
+    median = float(np.median(phi[phi > 1.0]))
+    print(f"Example 6 (96^3) t={f['t']}: median over phi > 1 {median:.5f}, centre {centre:.5f}")
+    assert round(median, f["decimals"]) == f["value"]
+    assert round(centre, f["decimals"]) == f["value"]
+    assert abs(median - math.sqrt(f["mu2"] / f["lambda"])) < 5e-3

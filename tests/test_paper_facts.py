@@ -68,3 +68,35 @@ def test_example5_no_bubble():
                  inv_L2=1.0 / f["L"] ** 2, callback=lambda n, t, p, q: worst.append(p.min()))
     assert min(worst) > -1e-12
 
+
+
+def example6_workload(n, dt):
+    import synth_inputs as si
+    f = FACTS["example6_positive_limit"]
+    p0, p1 = si.example6_data(n, f["bump_centre"], f["second_centre"], f["bump_radius"],
+                              f["phi0_amp"], f["phi1_amp"])
+    box = ((n, n, n), (0.0,) * 3, (1.0,) * 3)
+    return si.Workload(f"example6_{n}", *box, mu2=f["mu2"], lam=f["lambda"], dt=dt, steps=0,
+                       inv_L2=1.0 / f["L"] ** 2, phi0=lambda: p0, phi1=lambda: p1)
+
+
+def test_example6_positive_limit(oracle_mod):
+    """Example 6 on the 3-D oracle at 48^3 (the data are not radial): phi0's
+    negative lobe (down to ~-0.5) is gone by t = 4, and the positive region
+    sits at the Duffing equilibrium sqrt(9/2) ~ 2.12 (its median, and the
+    value at the bubble centre, round to the printed 2.12)."""
+    f = FACTS["example6_positive_limit"]
+    n, dt = 48, 2e-3
+    w = example6_workload(n, dt)
+    p0, _ = w.initial()
+    assert p0.min() < -0.4                       # the data change sign
+    phi, _ = oracle.solve_workload(w, nsteps=int(round(f["t"] / dt)))
+    top = phi.max()
+    c = n // 2
+    centre = phi[c - 1:c + 1, c - 1:c + 1, c - 1:c + 1].mean()
+    median = float(np.median(phi[phi > 1.0]))
+    assert phi.min() > -1e-2 * top               # what is left below 0: < 1% of the maximum
+    assert round(median, f["decimals"]) == f["value"]
+    assert round(centre, f["decimals"]) == f["value"]
+    # and not the other equilibria: the limit is the positive one
+    assert abs(median - np.sqrt(f["mu2"] / f["lambda"])) < 5e-3
