@@ -1,5 +1,5 @@
 """The paper's section 3 examples on the GPU path at reduced resolution
-(Examples 3, 4, 5 and 6).
+(Examples 1, 3, 4, 5 and 6).
 
 Unit box [0,1]^3 (cell-centred), L = 5 (inv_L2 = 1/25), the paper's bump
 B(x; C, R) = exp(1/R^2 - 1/(R^2 - |x-C|^2)) with C the box centre (Example
@@ -139,3 +139,54 @@ def test_example6_positive_limit(hb):
     assert round(median, f["decimals"]) == f["value"]
     assert round(centre, f["decimals"]) == f["value"]
     assert abs(median - math.sqrt(f["mu2"] / f["lambda"])) < 5e-3
+
+
+def test_example1_grid_convergence_and_precision(hb):
+    """Example 1 (phi0 = 3 B(x; C, 0.3), phi1 = 0, mu^2 = 9, lambda = 2): the
+    paper compares coarser grids with a finer one at t = 1 and t = 2 and sees
+    the differences shrink, and finds single against double precision close
+    and not growing in time.  Here n = 60 and 180 against 540 on the nodes the
+    three cell-centred grids share (ratio 3): the differences shrink, and by
+    the factor 3^p + 1 that a method of spatial order p gives, with p = 4
+    (section 2: the fourth-order stencil; dt = 1e-3 keeps the RK4 error far
+    below).  FP32c against FP64 at n = 180 stays below 1e-6 relative at both
+    times and does not grow."""
+    dt = 1e-3
+    ns = (60, 180, 540)
+
+    def run(n, prec):
+        w = unit_box_case(n, 3.0, 0.0, 0.3, 9.0, 2.0, dt)
+        k = int(round(1.0 / dt))
+        p0, p1 = w.initial()
+        h = hb.hb_create(hb.config_from_workload(w, prec))
+        out = []
+        try:
+            hb.hb_set_initial(h, p0, p1)
+            for _ in range(2):
+                hb.hb_step(h, k)
+                phi = np.empty_like(p0)
+                hb.hb_read(h, phi, None)
+                out.append(phi)
+        finally:
+            hb.hb_destroy(h)
+        return out
+
+    res = {n: run(n, 0) for n in ns}
+    for ti in range(2):
+        fine = res[540][ti]
+        # the nodes of the 60^3 grid, as they sit in each finer grid
+        on60 = {n: res[n][ti][(n // 60) // 2::n // 60, (n // 60) // 2::n // 60, (n // 60) // 2::n // 60]
+                for n in ns}
+        d60 = np.abs(on60[60] - on60[540]).max()
+        d180 = np.abs(on60[180] - on60[540]).max()
+        order = math.log(d60 / d180 - 1.0, 3.0)
+        print(f"Example 1, t={ti + 1}: max |phi_n - phi_540| on the 60^3 nodes: n=60 {d60:.3e}, "
+              f"n=180 {d180:.3e}; observed spatial order {order:.2f} (max |phi| {np.abs(fine).max():.3f})")
+        assert d180 < d60 < 1e-2 * np.abs(fine).max()
+        assert 3.7 < order < 4.3
+    a32 = run(180, 1)
+    diff = [np.abs(a32[i] - res[180][i]).max() / np.abs(res[180][i]).max() for i in range(2)]
+    print(f"Example 1 (180^3): FP32c vs FP64 relative max difference at t=1, 2: "
+          f"{diff[0]:.3e}, {diff[1]:.3e}")
+    assert max(diff) < 1e-6
+    assert diff[1] < 2 * diff[0]
