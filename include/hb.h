@@ -241,8 +241,9 @@ typedef struct hb_radial_config {
 
 #define HB_RADIAL_MAX_NODES 2700
 
-/* Advance `count` independent radial solves in one launch (one workgroup per
- * solve; every solve runs all its steps inside the kernel).  phi and psi hold
+/* Advance `count` independent radial solves together (one workgroup per
+ * solve; each launch runs up to 65536 steps of every solve inside the kernel,
+ * so a solve of at most that many steps takes one launch).  phi and psi hold
  * the solves' nodes back to back (solve k starts after the m of solves
  * 0..k-1), FP64, in `mem` (HB_HOST or HB_DEVICE); they are read as the
  * initial state and overwritten with the final state.  Waits for completion.

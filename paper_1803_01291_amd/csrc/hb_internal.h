@@ -105,7 +105,9 @@ struct RadialDesc {
     double dr, mu2, lambda, inv_L2, t0, dt;
 };
 size_t radial_lds_bytes(int max_m);
+// steps n0 <= n < min(n1, steps) of every solve (state read from and
+// written back to phi, psi)
 int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
-                  void* stream);
+                  long long n0, long long n1, void* stream);
 
 }  // namespace hb

@@ -31,7 +31,7 @@ using gptr = __attribute__((address_space(1))) T*;
 template <int NPT>
 __global__ void __launch_bounds__(RAD_THREADS)
 radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
-              double* __restrict__ psi) {
+              double* __restrict__ psi, long long n0, long long n1) {
     extern __shared__ double lds[];
     const RadialDesc d = descs[blockIdx.x];
     const int m = d.m;
@@ -88,7 +88,8 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
         }
     };
 
-    for (long long n = 0; n < d.steps; ++n) {
+    const long long nend = d.steps < n1 ? d.steps : n1;
+    for (long long n = n0; n < nend; ++n) {
         const double t = d.t0 + (double)n * dt;
         const double c1 = exp(-2.0 * t) * d.inv_L2;
         const double c2 = exp(-2.0 * (t + dt / 2.0)) * d.inv_L2;
@@ -165,14 +166,14 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
 
 template <int NPT>
 hipError_t launch_radial_t(const RadialDesc* descs, int count, size_t bytes, double* phi,
-                           double* psi, hipStream_t s) {
+                           double* psi, long long n0, long long n1, hipStream_t s) {
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)radial_kernel<NPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((radial_kernel<NPT>), dim3(count), dim3(RAD_THREADS), bytes, s, descs, phi,
-                       psi);
+                       psi, n0, n1);
     return hipGetLastError();
 }
 
@@ -181,17 +182,17 @@ hipError_t launch_radial_t(const RadialDesc* descs, int count, size_t bytes, dou
 size_t radial_lds_bytes(int max_m) { return (size_t)(2 * (max_m + 4)) * sizeof(double); }
 
 int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
-                  void* stream) {
+                  long long n0, long long n1, void* stream) {
     if (count <= 0) return 0;
     const size_t bytes = radial_lds_bytes(max_m);
     hipStream_t s = (hipStream_t)stream;
     const int npt = (max_m + RAD_THREADS - 1) / RAD_THREADS;
     hipError_t e;
-    if (npt <= 1) e = launch_radial_t<1>(descs, count, bytes, phi, psi, s);
-    else if (npt <= 2) e = launch_radial_t<2>(descs, count, bytes, phi, psi, s);
-    else if (npt <= 4) e = launch_radial_t<4>(descs, count, bytes, phi, psi, s);
-    else if (npt <= 8) e = launch_radial_t<8>(descs, count, bytes, phi, psi, s);
-    else if (npt <= 11) e = launch_radial_t<11>(descs, count, bytes, phi, psi, s);
+    if (npt <= 1) e = launch_radial_t<1>(descs, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 2) e = launch_radial_t<2>(descs, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 4) e = launch_radial_t<4>(descs, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 8) e = launch_radial_t<8>(descs, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 11) e = launch_radial_t<11>(descs, count, bytes, phi, psi, n0, n1, s);
     else return (int)hipErrorInvalidValue;
     return (int)e;
 }

@@ -613,10 +613,10 @@ int group_step(Group& g, long long k, bool use_graph, hipStream_t stream) {
 }
 
 int group_step_timed(Group& g, long long k, hipStream_t stream, double* stage_ms) {
-    hipEvent_t ev[5];
-    for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ev[i]));
-    double acc[4] = {0, 0, 0, 0};
+    hipEvent_t ev[5] = {};
     int rc = HB_OK;
+    for (int i = 0; i < 5 && rc == HB_OK; ++i) rc = from_hip(hipEventCreate(&ev[i]), "event create");
+    double acc[4] = {0, 0, 0, 0};
     const int nk = kernels_per_step(g);
     for (long long j = 0; j < k && rc == HB_OK; ++j) {
         rc = from_hip(hipEventRecord(ev[0], stream), "event record");
@@ -634,7 +634,8 @@ int group_step_timed(Group& g, long long k, hipStream_t stream, double* stage_ms
         if (rc == HB_OK)
             for (Solve* s : g.members) s->nstep = std::min(s->nstep + 1, s->target);
     }
-    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 5; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     if (stage_ms)
         for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i];
     return rc;
@@ -1340,6 +1341,8 @@ extern "C" int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, d
 
 // ---- batched radial solves ------------------------------------------------------
 
+constexpr long long RADIAL_CHUNK = 1LL << 16;
+
 extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi,
                                int mem, void* stream) {
     g_last_error.clear();
@@ -1348,7 +1351,7 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
     if (count == 0) return HB_OK;
     std::vector<RadialDesc> descs(count);
-    long long total = 0;
+    long long total = 0, max_steps = 0;
     int max_m = 0;
     for (int i = 0; i < count; ++i) {
         const hb_radial_config& c = cfgs[i];
@@ -1377,6 +1380,7 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
         d.dt = c.dt;
         total += c.m;
         max_m = std::max(max_m, c.m);
+        max_steps = std::max<long long>(max_steps, c.steps);
     }
     hipStream_t s = (hipStream_t)stream;
     const size_t bytes = (size_t)total * sizeof(double);
@@ -1384,11 +1388,17 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     double* dphi = nullptr;
     double* dpsi = nullptr;
     int rc = HB_OK;
-    if (hipMalloc((void**)&d_desc, descs.size() * sizeof(RadialDesc)) != hipSuccess)
+    if (hipMalloc((void**)&d_desc, descs.size() * sizeof(RadialDesc)) != hipSuccess) {
+        d_desc = nullptr;
+        (void)hipGetLastError();
         rc = fail(HB_E_NOMEM, "radial descriptor allocation");
-    if (rc == HB_OK && mem == HB_HOST) {
-        if (hipMalloc((void**)&dphi, bytes) != hipSuccess || hipMalloc((void**)&dpsi, bytes) != hipSuccess)
+    }
+    if (mem == HB_HOST) {
+        if (rc == HB_OK &&
+            (hipMalloc((void**)&dphi, bytes) != hipSuccess || hipMalloc((void**)&dpsi, bytes) != hipSuccess)) {
+            (void)hipGetLastError();
             rc = fail(HB_E_NOMEM, "radial state allocation");
+        }
     } else {
         dphi = phi;
         dpsi = psi;
@@ -1400,7 +1410,11 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
         rc = from_hip(hipMemcpyAsync(dphi, phi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
         if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(dpsi, psi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
     }
-    if (rc == HB_OK) rc = from_hip(launch_radial(d_desc, count, max_m, dphi, dpsi, s), "radial launch");
+    // launches of at most RADIAL_CHUNK steps each, so no single kernel runs
+    // for an unbounded time (the state goes through memory between them)
+    for (long long n0 = 0; rc == HB_OK && n0 < std::max<long long>(max_steps, 1); n0 += RADIAL_CHUNK)
+        rc = from_hip(launch_radial(d_desc, count, max_m, dphi, dpsi, n0, n0 + RADIAL_CHUNK, s),
+                      "radial launch");
     if (rc == HB_OK && mem == HB_HOST) {
         rc = from_hip(hipMemcpyAsync(phi, dphi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");
         if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(psi, dpsi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");

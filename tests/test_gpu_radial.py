@@ -204,3 +204,40 @@ def test_radial_sweep_full_size_sampled(hb):
         err = rel(phi[i * m:(i + 1) * m], psi[i * m:(i + 1) * m], *ref)
         print(f"sweep solve {i} (mu2 {mu2:.2f}, lambda {lam:.2f}): err {err:.3e}, floor {floor:.3e}")
         assert err <= tol
+
+
+def test_radial_steps_across_launches(hb):
+    """A solve longer than one launch's step range (65536 steps) runs in
+    several launches with its state in memory between them: it matches the
+    oracle, and a shorter solve of the same call stays bitwise what it is
+    alone (its state passes unchanged through the later launches)."""
+    # dt small enough that the dynamics (and c(t)) still move across the
+    # launch boundary, so a lost, repeated or mistimed step would show
+    long_case = (16, 0.05, 9.0, 2.0, 1 / 25, 0.0, 1e-5, 65536 + 700, 1.0, -5.0, 0.3)
+    short_case = (40, 0.02, 9.0, 2.0, 1 / 25, 0.0, 1e-3, 300, 1.0, -5.0, 0.3)
+    cfgs, p0s, p1s = [], [], []
+    for c in (long_case, short_case):
+        m, dr, mu2, lam, invL2, t0, dt, steps = c[:8]
+        cfgs.append(hb.make_radial_config(m, dr, mu2, lam, dt, steps, t0, invL2))
+        a, b = initial(c)
+        p0s.append(a)
+        p1s.append(b)
+    phi, psi = np.concatenate(p0s), np.concatenate(p1s)
+    hb.hb_radial_solve(cfgs, phi, psi)
+    m0 = long_case[0]
+    lp, ls = phi[:m0], psi[:m0]
+    sp, ss = p0s[1].copy(), p1s[1].copy()
+    hb.hb_radial_solve([cfgs[1]], sp, ss)
+    assert np.array_equal(phi[m0:], sp) and np.array_equal(psi[m0:], ss)
+    m, dr, mu2, lam, invL2, t0, dt, steps = long_case[:8]
+    at_boundary = {}
+
+    def keep(n, t, p, q):
+        if n == 65536:
+            at_boundary["s"] = (p.copy(), q.copy())
+
+    rp, rs = radial_solve(p0s[0], p1s[0], dr, mu2, lam, dt, steps, t0=t0, inv_L2=invL2, callback=keep)
+    assert rel(*at_boundary["s"], rp, rs) > 1e-4  # the steps after the boundary matter
+    err = rel(lp, ls, rp, rs)
+    print(f"radial m={m}, {steps} steps (two launches): rel err {err:.3e}")
+    assert err <= 1e-12
