@@ -26,7 +26,10 @@
  *    (host) or in stream order (device).
  *  - Handles are not thread-safe; distinct handles may be used concurrently.
  *  - All device work of a handle is ordered on its stream (hb_config.stream,
- *    or a stream the library creates when that is NULL).
+ *    or a stream the library creates when that is NULL).  A library-created
+ *    stream is non-blocking: it does not wait for work on other streams, so
+ *    device inputs produced elsewhere must be complete before the call, or
+ *    the producing stream must be the handle's stream.
  */
 #ifndef HB_H
 #define HB_H
