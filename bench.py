@@ -63,7 +63,7 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "b9ffbc3c407b2610"
+TRAFFIC_SOURCE_SHA = "e56f62406ac93ff4"
 TRAFFIC_BYTES_F64 = 576.6 * 2 ** 20
 
 
