@@ -158,9 +158,11 @@ int hb_diagnostics(hb_solver* s, hb_diag* out);
  * whole-step kernel, the length that best fills whole rounds of resident
  * blocks on the device); by in {8, 16}: rows of 64 columns per tile for the
  * stage-pair and per-stage kernels (default 16); for the whole-step kernel
- * by = 8 selects 32 x 24 tiles (1008-thread blocks) and by = 16 selects
- * 60 x 12 tiles (1024-thread blocks; the default).
- * Results do not depend on it. */
+ * by = 8 selects 32 x 24 tiles (1008-thread blocks), by = 16 selects 60 x 12
+ * tiles (1024-thread blocks) and by = 11 selects 64 x 11 tiles (1020-thread
+ * blocks; whole-step only, else HB_E_ARG).  The whole-step default is 60 x 12,
+ * or 64 x 11 where the library's model of block rounds gives it at least 5%
+ * less work (e.g. 256^3 and 512^3 grids).  Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 
 /* Time every candidate tile shape for `trial_steps` steps on the current

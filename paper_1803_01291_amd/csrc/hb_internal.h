@@ -61,13 +61,14 @@ int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* 
 // Whole-step kernel: one launch per RK4 step, on paired-state solves (cs = 2).
 // A block's threads own an rx x ry region: its interior tile of
 // (rx - 4) x (ry - 4) columns plus a 2-cell ring.  Shapes (`shape` indexes
-// this table), both 16 waves per CU: 36 x 28 (1008 threads; tiles 32 columns
-// wide, which cover power-of-two widths exactly) and 64 x 16 (1024 threads).
-// Bitwise equal to the stage-pair kernels.
+// this table), all 16 waves per CU: 36 x 28 (1008 threads; tiles 32 columns
+// wide), 64 x 16 (1024 threads; a region row is one wave) and 68 x 15 (1020
+// threads; tiles 64 columns wide, which cover multiples of 64 exactly and
+// start on 128-byte lines).  Bitwise equal to the stage-pair kernels.
 struct StepShape {
     int rx, ry, blocks_per_cu;
 };
-constexpr StepShape STEP_SHAPES[2] = {{36, 28, 1}, {64, 16, 1}};
+constexpr StepShape STEP_SHAPES[3] = {{36, 28, 1}, {64, 16, 1}, {68, 15, 1}};
 int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
                 long long kstep, void* stream);
 int launch_tick(SolveDesc* descs, int count, long long k, void* stream);

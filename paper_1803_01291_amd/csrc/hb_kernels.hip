@@ -1001,9 +1001,11 @@ hipError_t launch_step_t(int shape, const SolveDesc* descs, const Tile* tiles, i
                          long long kstep, hipStream_t s) {
     static_assert(STEP_SHAPES[0].rx == 36 && STEP_SHAPES[0].ry == 28, "shape table");
     static_assert(STEP_SHAPES[1].rx == 64 && STEP_SHAPES[1].ry == 16, "shape table");
+    static_assert(STEP_SHAPES[2].rx == 68 && STEP_SHAPES[2].ry == 15, "shape table");
     switch (shape) {
         case 0: return launch_step_shape<T, COMP, 36, 28>(descs, tiles, ntiles, kstep, s);
         case 1: return launch_step_shape<T, COMP, 64, 16>(descs, tiles, ntiles, kstep, s);
+        case 2: return launch_step_shape<T, COMP, 68, 15>(descs, tiles, ntiles, kstep, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -453,11 +453,10 @@ int device_cus() {
 }
 
 // whole-step kernel region shape (STEP_SHAPES): by = 8 selects 36 x 28
-// regions (32 x 24 tiles), by = 16 selects 64 x 16 regions (60 x 12 tiles).
-// Default 64 x 16: on 256^3 and 512^3 grids, FP64 and FP32c, it was as fast
-// or 5-13% faster on every device measured.
-int step_shape(int by) { return by == 16 ? 1 : 0; }
-int default_step_by(int) { return 16; }
+// regions (32 x 24 tiles), by = 16 selects 64 x 16 regions (60 x 12 tiles),
+// by = 11 selects 68 x 15 regions (64 x 11 tiles; whole-step scheme only).
+int step_shape(int by) { return by == 16 ? 1 : by == 11 ? 2 : 0; }
+bool valid_by(int by, int scheme) { return by == 8 || by == 16 || (by == 11 && scheme == SCHEME_STEP); }
 
 // z-march length for one solve.  Blocks run in rounds of (CUs x blocks per
 // CU); a march of zc planes costs about zc + 4 planes (warm-up) rounded up to
@@ -465,8 +464,11 @@ int default_step_by(int) { return 16; }
 // rounds x cost per block, so the last round is not mostly empty and the
 // warm-up planes stay a small share.  Batches keep 32-plane marches (their
 // many tiles already fill the rounds).
-int default_zc_step(const Layout& L, int by, int nmembers) {
-    if (nmembers > 1) return std::min(L.nz, 32);
+struct ZPlan {
+    int zc;
+    double cost;  // rounds x planes per block, in plane units
+};
+ZPlan plan_zc_step(const Layout& L, int by) {
     const StepShape sh = STEP_SHAPES[step_shape(by)];
     const long long tx = sh.rx - 4, ty = sh.ry - 4;
     const long long xy = ((L.nx + tx - 1) / tx) * ((L.ny + ty - 1) / ty);
@@ -483,7 +485,23 @@ int default_zc_step(const Layout& L, int by, int nmembers) {
             best = zc;
         }
     }
-    return best;
+    return {best, best_cost};
+}
+
+int default_zc_step(const Layout& L, int by, int nmembers) {
+    if (nmembers > 1) return std::min(L.nz, 32);
+    return plan_zc_step(L, by).zc;
+}
+
+// Default region shape of a single solve: 64 x 16, or 68 x 15 where the march
+// model gives it at least 5% fewer block-planes.  68 x 15 regions cost a few
+// percent more per block (rows are not waves) but their 64-column tiles cover
+// multiples of 64 without a ragged tile and start on 128-byte lines; measured
+// (FP64 / FP32c): 256^3 -3.5% / -1.5%, 512^3 -3% / -8%, 512 x 512 x 64 -6% /
+// -7% (model 13-22% fewer), 500^3, 384^3, 192^3 +2 to +4% (model 0-5% fewer,
+// so 64 x 16 stays).  Batches and pools keep 64 x 16.
+int default_step_by(const Layout& L) {
+    return plan_zc_step(L, 11).cost <= 0.95 * plan_zc_step(L, 16).cost ? 11 : 16;
 }
 
 void make_tiles(const Solve& s, int solve_index, int scheme, int by, int zc_req, int nmembers,
@@ -707,7 +725,7 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
     h->g.scheme = scheme_of(cfg->flags);
-    h->g.by = h->g.scheme == SCHEME_STEP ? default_step_by(cfg->precision) : DEFAULT_BY;
+    h->g.by = h->g.scheme == SCHEME_STEP ? default_step_by(h->s->L) : DEFAULT_BY;
     h->g.members.push_back(h->s.get());
     HIP_TRY(hipStreamSynchronize(h->stream));
     *out = h.release();
@@ -822,7 +840,7 @@ int hb_diagnostics(hb_solver* h, hb_diag* out) {
 
 int hb_set_tiling(hb_solver* h, int by, int zc) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
-    if (by != 8 && by != 16) return fail(HB_E_ARG, "by must be 8 or 16");
+    if (!valid_by(by, h->g.scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11, whole-step scheme)");
     if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
     h->g.by = by;
     h->g.zc = zc;
@@ -954,7 +972,7 @@ int group_autotune(Group& g, int trial_steps, hipStream_t stream, int* best_by, 
     int maxz = 0;
     for (Solve* s : g.members) maxz = std::max(maxz, s->L.nz);
     if (g.scheme == SCHEME_STEP) {
-        for (int by : {16, 8})
+        for (int by : {16, 11, 8})
             for (int zc : {0, 16, 32, 64, 128, 256})
                 if (zc <= maxz) cand.push_back({by, zc});
     } else {
@@ -1051,7 +1069,7 @@ int hb_batch_create(int count, const hb_config* cfgs, void* stream, hb_batch** o
         if (i == 0)
             for (Group& g : b->groups) {
                 g.scheme = scheme_of(cfgs[i].flags);
-                g.by = g.scheme == SCHEME_STEP ? default_step_by(g.prec) : DEFAULT_BY;
+                g.by = DEFAULT_BY;  // 64 x 16 regions for the whole-step scheme
             }
         b->use_graph = b->use_graph || (cfgs[i].flags & HB_USE_GRAPH);
         b->solves.push_back(std::move(s));
@@ -1107,7 +1125,7 @@ int hb_batch_sync(hb_batch* b) {
 
 int hb_batch_set_tiling(hb_batch* b, int by, int zc) {
     if (!b) return fail(HB_E_ARG, "batch is NULL");
-    if (by != 8 && by != 16) return fail(HB_E_ARG, "by must be 8 or 16");
+    if (!valid_by(by, b->groups[0].scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11, whole-step scheme)");
     if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
     for (Group& g : b->groups) {
         g.by = by;
@@ -1169,7 +1187,7 @@ int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out
     }
     p->groups[0].prec = HB_F64;
     p->groups[1].prec = HB_F32C;
-    for (Group& g : p->groups) g.by = default_step_by(g.prec);  // whole-step scheme
+    for (Group& g : p->groups) g.by = DEFAULT_BY;  // whole-step scheme: 64 x 16 regions
     *out = p.release();
     return HB_OK;
 }

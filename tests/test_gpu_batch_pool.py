@@ -149,7 +149,7 @@ def test_autotune_restores_state_bitwise(hb):
         hb.hb_set_initial(h, p0, p1)
         hb.hb_step(h, 2)
         by, zc = hb.hb_autotune(h, 2)
-        assert by in (8, 16) and zc >= 0
+        assert by in (8, 11, 16) and zc >= 0
         assert hb.hb_time(h)[1] == 2
         hb.hb_step(h, 4)
         phi, psi = np.empty_like(p0), np.empty_like(p0)

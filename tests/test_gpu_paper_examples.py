@@ -1,5 +1,5 @@
 """The paper's section 3 examples on the GPU path at reduced resolution
-(Examples 1, 3, 4, 5 and 6).
+(Examples 1, 3, 4, 5, 6 and 7).
 
 Unit box [0,1]^3 (cell-centred), L = 5 (inv_L2 = 1/25), the paper's bump
 B(x; C, R) = exp(1/R^2 - 1/(R^2 - |x-C|^2)) with C the box centre (Example
@@ -190,3 +190,16 @@ def test_example1_grid_convergence_and_precision(hb):
           f"{diff[0]:.3e}, {diff[1]:.3e}")
     assert max(diff) < 1e-6
     assert diff[1] < 2 * diff[0]
+
+
+def test_example7_parity(hb, oracle_mod):
+    """Example 7's two-bump data (the paper's longest run, benchmarked at its
+    500^3 grid): GPU against the oracle at 64^3, dt = 1e-3, 150 steps (past
+    the sign changes near t = 0.12), every node."""
+    w = si.example7_config(64, 150)
+    w.dt = 1e-3
+    (phi, psi, d), = run_segments(hb, w, [150])
+    err = oracle.rel_maxnorm(phi, psi, *oracle.solve_workload(w, nsteps=150))
+    print(f"Example 7 (64^3 x 150): relative max-norm error {err:.3e}, negative nodes {d['negative']}")
+    assert err <= 1e-12
+    assert phi.min() < -0.01 * phi.max()   # the bubbles have formed

@@ -40,6 +40,9 @@ def test_config1_full(hb, oracle_mod):
     ((5, 3, 30), (8, 4)),          # narrower than one tile
     ((97, 53, 41), (8, 0)),        # 4 x 3 tiles, every axis ragged (1, 5, z)
     ((125, 50, 29), (16, 9)),      # 3 x 5 tiles of 60 x 12, ragged in all axes
+    ((130, 25, 19), (11, 6)),      # 3 x 3 tiles of 64 x 11 (ragged 2, 3), z ragged 1
+    ((64, 11, 7), (11, 0)),        # exactly one 64 x 11 tile
+    ((256, 23, 12), (11, 5)),      # 4 whole 64-column tiles, y ragged 1
 ])
 def test_ragged_shapes(hb, oracle_mod, shape, tiling):
     w = si.small_case(*shape, seed=sum(shape), steps=12)
@@ -124,7 +127,10 @@ def test_other_schemes_vs_oracle(hb, oracle_mod, flags):
 def test_tiling_does_not_change_results(hb, flags):
     w = si.small_case(90, 30, 33, seed=9, steps=6)
     ref = run_gpu(hb, w, tiling=(8, 0), flags=flags)
-    for t in [(16, 0), (8, 5), (16, 11), (8, 1), (16, 2)]:
+    shapes = [(16, 0), (8, 5), (16, 11), (8, 1), (16, 2)]
+    if flags == 0:  # the 64 x 11 tiles of the whole-step kernel
+        shapes += [(11, 0), (11, 4), (11, 1)]
+    for t in shapes:
         got = run_gpu(hb, w, tiling=t, flags=flags)
         np.testing.assert_array_equal(ref[0], got[0])
         np.testing.assert_array_equal(ref[1], got[1])
@@ -233,6 +239,18 @@ def test_errors(hb):
         assert e.value.code == hb.HB_E_ARG
         hb.hb_step(h, 1)  # still usable
         assert hb.hb_time(h)[1] == 1
+        for by in (0, 12, 32):
+            with pytest.raises(hb.HBError) as e:
+                hb.hb_set_tiling(h, by, 0)
+            assert e.value.code == hb.HB_E_ARG
+    finally:
+        hb.hb_destroy(h)
+    # 64 x 11 tiles exist for the whole-step kernel only
+    h = hb.hb_create(hb.config_from_workload(w, flags=hb.HB_PAIRWISE))
+    try:
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_set_tiling(h, 11, 0)
+        assert e.value.code == hb.HB_E_ARG
     finally:
         hb.hb_destroy(h)
     bad = hb.config_from_workload(w)
