@@ -31,6 +31,10 @@ Prints ONE JSON line.  Extra objects:
                    eight), timed like the main leg;
   radial        -- the batched radial parameter sweep (4096 solves) against
                    its LDS roofline;
+  paper_grid    -- the paper's longest run (section 3, Example 7) at its
+                   default grid, 500^3 cells, dt = 1e-4, FP64 and FP32c: step
+                   rate and the projected hours to t = 50 (5e5 steps) beside
+                   the paper's 27 h;
   paper_context -- the paper's own K40c rate (context, not a baseline).
 """
 import argparse
@@ -63,8 +67,8 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "e56f62406ac93ff4"
-TRAFFIC_BYTES_F64 = 576.6 * 2 ** 20
+TRAFFIC_SOURCE_SHA = "45ec8342edc25425"
+TRAFFIC_BYTES_F64 = 611.3 * 2 ** 20
 
 
 def source_sha():
@@ -183,6 +187,24 @@ def run_shard(steps, warmup):
             "own_GBps": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9}
 
 
+def run_paper_grid(steps, warmup):
+    """The paper's longest run at its default grid: Example 7 on 500^3 cells
+    of the unit box, dt = 1e-4 (section 3), FP64 and FP32c, `steps` steps
+    timed like the main leg.  The hours to t = 50 (5e5 steps) are projected
+    from the measured step time, beside the paper's 27 h on one Tesla K40c."""
+    import synth_inputs as si
+    w = si.example7_config(500, steps)
+    out = {"grid": list(w.n), "dt": w.dt, "steps": steps, "paper_hours_to_t50": 27.0}
+    for prec, name in ((0, "f64"), (1, "f32c")):
+        elapsed, stage_ms, d = run_gpu(w, prec, steps, warmup, 10)
+        ms = elapsed / steps * 1e3
+        out[name] = {"pt_updates_per_s": w.points * steps / elapsed, "ms_per_step": ms,
+                     "kernel_ms": sum(stage_ms),
+                     "projected_hours_to_t50": 5e5 * ms / 3.6e6,
+                     "nonfinite": d["nonfinite"]}
+    return out
+
+
 # radial batch kernel: LDS bytes per node-step (per stage one write of the
 # stage input and five stencil reads, 8 B each; the state stays in registers)
 # and the LDS peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
@@ -266,6 +288,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-radial", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
+    ap.add_argument("--no-paper-grid", action="store_true",
+                    help="skip the paper's default-grid leg (Example 7, 500^3, dt 1e-4)")
     ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
                     help="3-D scheme of the single-solve legs: the whole-step kernel (default) "
                          "or, for comparison, the stage-pair or per-stage kernels")
@@ -368,6 +392,8 @@ def main():
                   file=sys.stderr, flush=True)
     if not args.no_shard:
         out["shard"] = run_shard(200, 10)
+    if not args.no_paper_grid:
+        out["paper_grid"] = run_paper_grid(200, 10)
     if not args.no_radial:
         out["radial"] = run_radial(args.radial_count, 1000, args.radial_steps,
                                    0 if args.no_cpu else 4)
