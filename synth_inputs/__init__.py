@@ -35,7 +35,7 @@ __all__ = [
     "axis_nodes", "grid_mesh", "gaussian_sum", "cinf_bump", "paper_bump",
     "radial_gaussian", "Workload", "config1", "config2", "config3",
     "batch_config", "serving_trace", "ServeRequest", "small_case", "wide_plane",
-    "slab_config", "example6_data",
+    "slab_config", "example6_data", "example7_config",
 ]
 
 
@@ -118,6 +118,30 @@ def example6_data(n: int, C, C2, R: float, a0: float, a1: float):
     b1 = paper_bump(nn, lo, hi, C, R)
     b2 = paper_bump(nn, lo, hi, C2, R)
     return a0 * b1 * b2 * np.sin(2.0 * np.pi * X), a1 * b1
+
+
+def example7_config(n: int = 500, steps: int = 200):
+    """Section 3, Example 7 at the section's default grid (``n``^3 cells on the
+    unit box, dt = 1e-4, L = 5): ``phi0 = B(x; (0.4,)*3, 0.2) + B(x; (0.6,)*3,
+    0.2)``, ``phi1 = -5 phi0``, ``lambda = mu^2 = 0.1`` -- the paper's longest
+    run (to t = 50)."""
+    nn, lo, hi = (n, n, n), (0.0,) * 3, (1.0,) * 3
+
+    cache = {}
+
+    def bumps():  # evaluated once per workload (500^3 takes seconds)
+        if "b" not in cache:
+            cache["b"] = paper_bump(nn, lo, hi, (0.4,) * 3, 0.2) + paper_bump(nn, lo, hi, (0.6,) * 3, 0.2)
+        return cache["b"]
+
+    def phi0():
+        return bumps().copy()
+
+    def phi1():
+        return -5.0 * bumps()
+
+    return Workload(f"paper_example7_{n}", nn, lo, hi, mu2=0.1, lam=0.1, dt=1e-4, steps=steps,
+                    inv_L2=1.0 / 25.0, phi0=phi0, phi1=phi1)
 
 
 @dataclasses.dataclass
