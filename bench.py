@@ -68,6 +68,7 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
 TRAFFIC_SOURCE_SHA = "45ec8342edc25425"
+TRAFFIC_KERNEL = "step_kernel<double, false, 68, 15>"  # the 256^3 default region shape
 TRAFFIC_BYTES_F64 = 611.3 * 2 ** 20
 
 

@@ -175,13 +175,30 @@ int hb_autotune(hb_solver* s, int trial_steps, int* by, int* zc);
 int hb_destroy(hb_solver* s);
 
 /* Device bytes hb_create would allocate for cfg (0 on invalid cfg): per
- * field, the padded grid; the whole-step scheme allocates Y_phi and Y_psi
- * twice (step parity) plus, for HB_F32C, the two FP32 low parts (32 B or 24 B
- * per padded cell); HB_PAIRWISE and HB_STAGEWISE add the G1..G3 fields. */
+ * field, the padded grid; the whole-step scheme keeps a cell's state in one
+ * 16-byte slot per step parity, (phi, psi) in FP64 or (phi hi, psi hi, phi
+ * lo, psi lo) in FP32c (32 B per padded cell either way); HB_PAIRWISE and
+ * HB_STAGEWISE keep separate fields and add G1..G3. */
 size_t hb_footprint(const hb_config* cfg);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* hb_last_error(void);
+
+/* Device memory allocator for every later allocation of the library (solve
+ * state, coefficient tables, tile tables, staging and diagnostics buffers,
+ * batches, pools, radial batches; not the bandwidth probe), so that a
+ * framework's caching allocator can own it.  alloc(ctx, bytes, stream)
+ * returns device memory on the current device, aligned to at least 256
+ * bytes, for work ordered on `stream` (a hipStream_t, NULL for the null
+ * stream), or NULL on failure (the call then fails with HB_E_NOMEM);
+ * release(ctx, ptr, bytes) takes it back, and is called only after `stream`
+ * has finished all work on it.  Every block goes back through the allocator
+ * that made it, even after another is installed.  Both NULL restores
+ * hipMalloc/hipFree; one NULL is HB_E_ARG.  Process-wide; the functions may
+ * be called from any thread that calls the library. */
+typedef void* (*hb_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*hb_free_fn)(void* ctx, void* ptr, size_t bytes);
+int hb_set_allocator(hb_alloc_fn alloc, hb_free_fn release, void* ctx);
 
 /* ---- batched form: many independent solves in shared launches -------------- */
 

@@ -12,9 +12,11 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/hb.h"
@@ -61,15 +63,74 @@ long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 // 35 TB table).
 constexpr long long MAX_STEPS = 1LL << 40;
 
-// device allocation; a failure is HB_E_NOMEM and leaves no sticky HIP error
-int dev_alloc(void** p, size_t bytes, const char* what) {
+// ---- device memory: hipMalloc, or the caller's allocator (hb_set_allocator) ----
+
+struct AllocHook {
+    hb_alloc_fn alloc = nullptr;
+    hb_free_fn release = nullptr;
+    void* ctx = nullptr;
+};
+struct Hooked {
+    AllocHook hook;  // the allocator that made it, and must free it
+    size_t bytes;
+    hipStream_t stream;  // the stream it was allocated for
+};
+std::mutex g_alloc_mu;
+AllocHook g_hook;
+std::unordered_map<void*, Hooked> g_hooked;
+
+// device allocation of `bytes` for work on `stream`; a failure is HB_E_NOMEM
+// and leaves no sticky HIP error
+int dev_alloc(void** p, size_t bytes, const char* what, hipStream_t stream) {
     *p = nullptr;
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        h = g_hook;
+    }
+    if (h.alloc) {
+        void* q = h.alloc(h.ctx, bytes, (void*)stream);
+        if (!q) return fail(HB_E_NOMEM, "%s (%zu bytes): the installed allocator returned NULL", what, bytes);
+        if ((uintptr_t)q % 256 != 0) {
+            h.release(h.ctx, q, bytes);
+            return fail(HB_E_NOMEM, "%s: the installed allocator returned memory not aligned to 256 bytes",
+                        what);
+        }
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_hooked[q] = Hooked{h, bytes, stream};
+        *p = q;
+        return HB_OK;
+    }
     if (hipMalloc(p, bytes) != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(HB_E_NOMEM, "%s (%zu bytes): device allocation failed", what, bytes);
     }
     return HB_OK;
+}
+
+// free what dev_alloc returned (NULL-safe) through the allocator that made
+// it.  Memory from an installed allocator is handed back only once the stream
+// it was allocated for has drained (hipFree waits for the device by itself).
+void dev_free(void* p) {
+    if (!p) return;
+    Hooked rec{};
+    bool hooked = false;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        auto it = g_hooked.find(p);
+        if (it != g_hooked.end()) {
+            rec = it->second;
+            hooked = true;
+            g_hooked.erase(it);
+        }
+    }
+    if (hooked) {
+        (void)hipStreamSynchronize(rec.stream);
+        rec.hook.release(rec.hook.ctx, p, rec.bytes);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 // ---- layout ------------------------------------------------------------------
@@ -192,8 +253,8 @@ struct Solve {
     double h[3]{};
 
     ~Solve() {
-        if (mem) (void)hipFree(mem);
-        if (ctab) (void)hipFree(ctab);
+        dev_free(mem);
+        dev_free(ctab);
     }
     int prec() const { return cfg.precision; }
     // FP32c low parts of phi (k = 0) or psi (k = 1) of the state at step
@@ -224,12 +285,7 @@ int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
     for (int d = 0; d < 3; ++d) s.h[d] = (c.hi[d] - c.lo[d]) / c.n[d];
     const size_t fb = field_bytes(s.L);
     const size_t total = fb * (size_t)s.L.nfields;
-    hipError_t e = hipMalloc((void**)&s.mem, total);
-    if (e != hipSuccess) {
-        s.mem = nullptr;
-        (void)hipGetLastError();
-        return fail(HB_E_NOMEM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
-    }
+    HB_TRY(dev_alloc((void**)&s.mem, total, "solve state", stream));
     // zero everything once: the halo stays zero for the life of the solve
     HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
     const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
@@ -274,15 +330,15 @@ int ensure_ctab(Solve& s, long long need, hipStream_t stream, bool* reallocated)
         return fail(HB_E_NOMEM, "coefficient table for %lld steps: host allocation failed", cap);
     }
     double* nt = nullptr;
-    HB_TRY(dev_alloc((void**)&nt, host.size() * sizeof(double), "coefficient table"));
+    HB_TRY(dev_alloc((void**)&nt, host.size() * sizeof(double), "coefficient table", stream));
     hipError_t e = hipStreamSynchronize(stream);
     if (e == hipSuccess)
         e = hipMemcpy(nt, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(nt);
+        dev_free(nt);
         return fail(HB_E_HIP, "coefficient table upload: %s", hipGetErrorString(e));
     }
-    if (s.ctab) HIP_TRY(hipFree(s.ctab));
+    dev_free(s.ctab);
     s.ctab = nt;
     s.ctab_steps = cap;
     if (reallocated) *reallocated = true;
@@ -340,10 +396,10 @@ int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const vo
         const void* dsrc = src[k];
         void* staged = nullptr;
         if (src[k] && mem == HB_HOST) {
-            HB_TRY(dev_alloc(&staged, bytes, "staging buffer"));
+            HB_TRY(dev_alloc(&staged, bytes, "staging buffer", stream));
             hipError_t e = hipMemcpyAsync(staged, src[k], bytes, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) {
-                (void)hipFree(staged);
+                dev_free(staged);
                 return fail(HB_E_HIP, "H2D copy failed: %s", hipGetErrorString(e));
             }
             dsrc = staged;
@@ -353,7 +409,7 @@ int upload_state(Solve& s, int slot_phi, int slot_psi, const void* phi, const vo
         if (staged) {
             // the host copy and the unpack must finish before the staging buffer goes
             hipError_t e = hipStreamSynchronize(stream);
-            (void)hipFree(staged);
+            dev_free(staged);
             if (e != hipSuccess) return fail(HB_E_HIP, "sync failed: %s", hipGetErrorString(e));
         }
         HB_TRY(from_hip(r, "unpack"));
@@ -378,13 +434,13 @@ int download_state(Solve& s, void* phi, void* psi, int mem, int dtype, hipStream
                             "pack"));
         } else {
             void* staged = nullptr;
-            HB_TRY(dev_alloc(&staged, bytes, "staging buffer"));
+            HB_TRY(dev_alloc(&staged, bytes, "staging buffer", stream));
             int r = launch_pack(s.prec(), dtype, staged, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz,
                                 s.L.cs, hi[k], lo[k], stream);
             hipError_t e = r ? (hipError_t)r : hipMemcpyAsync(dst[k], staged, bytes,
                                                               hipMemcpyDeviceToHost, stream);
             hipError_t e2 = hipStreamSynchronize(stream);
-            (void)hipFree(staged);
+            dev_free(staged);
             if (e != hipSuccess) return fail(HB_E_HIP, "D2H failed: %s", hipGetErrorString(e));
             if (e2 != hipSuccess) return fail(HB_E_HIP, "sync failed: %s", hipGetErrorString(e2));
         }
@@ -432,8 +488,8 @@ struct Group {
     }
     void release() {
         drop_graph();
-        if (d_desc) (void)hipFree(d_desc);
-        if (d_tiles) (void)hipFree(d_tiles);
+        dev_free(d_desc);
+        dev_free(d_tiles);
         d_desc = nullptr;
         d_tiles = nullptr;
         desc_cap = tile_cap = 0;
@@ -539,25 +595,19 @@ int group_rebuild(Group& g, hipStream_t stream) {
     }
     HIP_TRY(hipStreamSynchronize(stream));
     if ((int)descs.size() > g.desc_cap) {
-        if (g.d_desc) HIP_TRY(hipFree(g.d_desc));
+        dev_free(g.d_desc);
         g.d_desc = nullptr;
+        g.desc_cap = 0;
         const int cap = std::max<int>(1, (int)descs.size());
-        if (hipMalloc((void**)&g.d_desc, cap * sizeof(SolveDesc)) != hipSuccess) {
-            (void)hipGetLastError();
-            g.desc_cap = 0;
-            return fail(HB_E_NOMEM, "descriptor allocation failed");
-        }
+        HB_TRY(dev_alloc((void**)&g.d_desc, cap * sizeof(SolveDesc), "descriptors", stream));
         g.desc_cap = cap;
     }
     if ((int)tiles.size() > g.tile_cap) {
-        if (g.d_tiles) HIP_TRY(hipFree(g.d_tiles));
+        dev_free(g.d_tiles);
         g.d_tiles = nullptr;
+        g.tile_cap = 0;
         const int cap = std::max<int>(1, (int)tiles.size());
-        if (hipMalloc((void**)&g.d_tiles, cap * sizeof(Tile)) != hipSuccess) {
-            (void)hipGetLastError();
-            g.tile_cap = 0;
-            return fail(HB_E_NOMEM, "tile table allocation failed");
-        }
+        HB_TRY(dev_alloc((void**)&g.d_tiles, cap * sizeof(Tile), "tile table", stream));
         g.tile_cap = cap;
     }
     if (!descs.empty())
@@ -689,8 +739,8 @@ struct hb_solver {
     int nparts = 0;
     ~hb_solver() {
         g.release();
-        if (d_partials) (void)hipFree(d_partials);
-        if (d_diag) (void)hipFree(d_diag);
+        dev_free(d_partials);
+        dev_free(d_diag);
         s.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -699,6 +749,14 @@ struct hb_solver {
 extern "C" {
 
 const char* hb_last_error(void) { return g_last_error.c_str(); }
+
+int hb_set_allocator(hb_alloc_fn alloc, hb_free_fn release, void* ctx) {
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(HB_E_ARG, "give both an allocation and a release function, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_hook = AllocHook{alloc, release, alloc ? ctx : nullptr};
+    return HB_OK;
+}
 
 size_t hb_footprint(const hb_config* cfg) {
     if (!cfg) return 0;
@@ -806,12 +864,12 @@ int hb_diagnostics(hb_solver* h, hb_diag* out) {
     if (!s.has_initial) return fail(HB_E_STATE, "no initial data");
     if (!h->built) HB_TRY(solver_rebuild(h));
     if (!h->d_partials || !h->d_diag) {  // both, or again after a failed allocation
-        if (h->d_partials) (void)hipFree(h->d_partials);
+        dev_free(h->d_partials);
         h->d_partials = nullptr;
         h->nparts = diag_partials_needed(s.L.nx, s.L.ny, s.L.nz);
         HB_TRY(dev_alloc((void**)&h->d_partials, (size_t)h->nparts * DIAG_COUNT * sizeof(double),
-                         "diagnostics partials"));
-        HB_TRY(dev_alloc((void**)&h->d_diag, DIAG_COUNT * sizeof(double), "diagnostics"));
+                         "diagnostics partials", h->stream));
+        HB_TRY(dev_alloc((void**)&h->d_diag, DIAG_COUNT * sizeof(double), "diagnostics", h->stream));
     }
     const double t = s.cfg.t0 + (double)s.nstep * s.cfg.dt;
     const double c = std::exp(-2.0 * t) * s.cfg.inv_L2;
@@ -901,8 +959,7 @@ void cache_store(const std::string& key, int by, int zc) {
 struct Snapshot {
     std::vector<void*> bufs;
     ~Snapshot() {
-        for (void* b : bufs)
-            if (b) (void)hipFree(b);
+        for (void* b : bufs) dev_free(b);
     }
 };
 
@@ -929,7 +986,7 @@ int snapshot_take(Group& g, Snapshot& snap, hipStream_t stream) {
         const size_t fb = field_bytes(s->L);
         for (char* base : state_fields(*s, (int)(s->nstep & 1))) {
             void* b = nullptr;
-            HB_TRY(dev_alloc(&b, fb, "autotune snapshot"));
+            HB_TRY(dev_alloc(&b, fb, "autotune snapshot", stream));
             snap.bufs.push_back(b);
             HIP_TRY(hipMemcpyAsync(b, base, fb, hipMemcpyDeviceToDevice, stream));
         }
@@ -1406,17 +1463,10 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     double* dphi = nullptr;
     double* dpsi = nullptr;
     int rc = HB_OK;
-    if (hipMalloc((void**)&d_desc, descs.size() * sizeof(RadialDesc)) != hipSuccess) {
-        d_desc = nullptr;
-        (void)hipGetLastError();
-        rc = fail(HB_E_NOMEM, "radial descriptor allocation");
-    }
+    rc = dev_alloc((void**)&d_desc, descs.size() * sizeof(RadialDesc), "radial descriptors", s);
     if (mem == HB_HOST) {
-        if (rc == HB_OK &&
-            (hipMalloc((void**)&dphi, bytes) != hipSuccess || hipMalloc((void**)&dpsi, bytes) != hipSuccess)) {
-            (void)hipGetLastError();
-            rc = fail(HB_E_NOMEM, "radial state allocation");
-        }
+        if (rc == HB_OK) rc = dev_alloc((void**)&dphi, bytes, "radial state", s);
+        if (rc == HB_OK) rc = dev_alloc((void**)&dpsi, bytes, "radial state", s);
     } else {
         dphi = phi;
         dpsi = psi;
@@ -1439,10 +1489,10 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     }
     hipError_t e = hipStreamSynchronize(s);
     if (rc == HB_OK && e != hipSuccess) rc = fail(HB_E_HIP, "radial sync: %s", hipGetErrorString(e));
-    if (d_desc) (void)hipFree(d_desc);
+    dev_free(d_desc);
     if (mem == HB_HOST) {
-        if (dphi) (void)hipFree(dphi);
-        if (dpsi) (void)hipFree(dpsi);
+        dev_free(dphi);
+        dev_free(dpsi);
     }
     return rc;
 }

@@ -83,6 +83,7 @@ _SIGS = {
     "hb_destroy": [_P],
     "hb_footprint": [ctypes.POINTER(hb_config)],
     "hb_last_error": [],
+    "hb_set_allocator": [_P, _P, _P],
     "hb_batch_create": [_I, ctypes.POINTER(hb_config), _P, ctypes.POINTER(_P)],
     "hb_batch_set_initial": [_P, _I, _P, _P, _I, _I],
     "hb_batch_step": [_P, _I64],
@@ -286,6 +287,56 @@ def hb_footprint(cfg: hb_config) -> int:
 
 def hb_last_error() -> str:
     return load().hb_last_error().decode()
+
+
+# ---- device allocator -------------------------------------------------------------
+
+HB_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+HB_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+# Every installed pair stays alive: the library hands each block back through
+# the allocator that made it, also after another one is installed.
+_HOOKS: list = []
+
+
+def hb_set_allocator(alloc=None, release=None) -> None:
+    """Install Python callables ``alloc(nbytes, stream) -> device address``
+    (an int; 0 or an exception means failure) and ``release(ptr, nbytes)`` as
+    the library's device allocator; both None restores hipMalloc/hipFree."""
+    if (alloc is None) != (release is None):
+        raise ValueError("hb_set_allocator: give both functions or neither")
+    if alloc is None:
+        _check(load().hb_set_allocator(None, None, None))
+        return
+
+    def _alloc(_ctx, nbytes, stream):
+        try:
+            return int(alloc(int(nbytes), stream or 0)) or None
+        except Exception:
+            return None
+
+    def _release(_ctx, ptr, nbytes):
+        try:
+            release(int(ptr), int(nbytes))
+        except Exception:
+            pass
+
+    pair = (HB_ALLOC_FN(_alloc), HB_FREE_FN(_release))
+    _HOOKS.append(pair)
+    _check(load().hb_set_allocator(ctypes.cast(pair[0], _P), ctypes.cast(pair[1], _P), None))
+
+
+def use_torch_allocator() -> None:
+    """Let torch's caching allocator own the library's device memory (blocks
+    are tied to the stream the library allocates them for)."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), stream)
+
+    def release(ptr, _nbytes):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hb_set_allocator(alloc, release)
 
 
 # ---- batched form -----------------------------------------------------------------

@@ -26,6 +26,6 @@ def test_traffic_constant_matches_the_committed_profile():
     sha = re.search(r"bench\.source_sha\(\)\): `([0-9a-f]+)`", prof).group(1)
     assert sha == bench.TRAFFIC_SOURCE_SHA
     # the traffic table's row: raw fetch, scaled fetch, write, total (MiB)
-    row = re.search(r"^\| `step_kernel<double, false, 64, 16>` \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|$",
-                    prof, flags=re.M)
+    row = re.search(r"^\| `" + re.escape(bench.TRAFFIC_KERNEL) +
+                    r"` \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|$", prof, flags=re.M)
     assert abs(float(row.group(4)) * 2 ** 20 - bench.TRAFFIC_BYTES_F64) < 0.05 * 2 ** 20

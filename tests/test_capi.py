@@ -107,3 +107,15 @@ def test_binding_rejects_wrong_array_sizes(lib):
     cfg = hb.make_radial_config(100, 1e-3, 1.0, 1.0, 1e-5, 1)
     with pytest.raises(ValueError, match="nodes"):
         hb.hb_radial_solve([cfg, cfg], np.zeros(150), np.zeros(200))
+
+
+def test_allocator_hook_arguments(lib):
+    """hb_set_allocator takes both functions or neither (host-only check)."""
+    import ctypes
+    from paper_1803_01291_amd import hb
+    cb = hb.HB_ALLOC_FN(lambda ctx, n, s: None)
+    assert lib.hb_set_allocator(ctypes.cast(cb, ctypes.c_void_p), None, None) == hb.HB_E_ARG
+    assert "both" in hb.hb_last_error()
+    assert lib.hb_set_allocator(None, None, None) == hb.HB_OK
+    with pytest.raises(ValueError):
+        hb.hb_set_allocator(lambda n, s: 0, None)
