@@ -72,6 +72,10 @@ extern "C" {
 #define HB_PAIRWISE 8u       /* one launch per stage pair (10 passes per step) */
                              /* instead of the default whole-step launch (4   */
                              /* passes); bitwise-equal results                */
+#define HB_BC_PERIODIC 16u   /* periodic boundaries on every axis instead of  */
+                             /* the zero 2-cell halo (a test configuration:   */
+                             /* e.g. constant data then follows the damped    */
+                             /* Duffing ODE); whole-step scheme only          */
 
 typedef struct hb_config {
     int32_t n[3];        /* interior points along x, y, z (each >= 1)              */

@@ -35,20 +35,33 @@ diag_kernel(const SolveDesc* __restrict__ d, int par, double c, double* __restri
     const float* LP = d->cs == 4 ? (const float*)P + 2 : d->lo_phi;
     const float* LS = d->cs == 4 ? (const float*)S + 2 : d->lo_psi;
     const double w0 = d->w0, mu2 = d->mu2, lam = d->lambda;
+    // element offset of cell (x, y, z); periodic solves wrap it into the
+    // interior, zero-halo solves read the halo
+    const bool per = d->periodic != 0;
+    auto off = [&](int x, int y, int z) -> long long {
+        if (per) {
+            x = ((x % nx) + nx) % nx;
+            y = ((y % ny) + ny) % ny;
+            z = ((z % nz) + nz) % nz;
+        }
+        return ((long long)z * sz + (long long)y * sy + x) * cs;
+    };
     double acc[DIAG_COUNT];
     for (int k = 0; k < DIAG_COUNT; ++k) acc[k] = 0.0;
     const long long rows = (long long)ny * nz;
     for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
         const int y = (int)(row % ny), z = (int)(row / ny);
         for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const long long o = ((long long)z * sz + (long long)y * sy + x) * cs;
+            const long long o = off(x, y, z);
             const double p = fld<COMP>(P, LP, o);
             const double s = fld<COMP>(S, LS, o);
             double lap = w0 * p;
-            const long long st[3] = {cs, sy * cs, sz * cs};
             for (int a = 0; a < 3; ++a) {
-                lap += d->w1[a] * (fld<COMP>(P, LP, o - st[a]) + fld<COMP>(P, LP, o + st[a]));
-                lap += d->w2[a] * (fld<COMP>(P, LP, o - 2 * st[a]) + fld<COMP>(P, LP, o + 2 * st[a]));
+                const int ex = a == 0, ey = a == 1, ez = a == 2;
+                lap += d->w1[a] * (fld<COMP>(P, LP, off(x - ex, y - ey, z - ez)) +
+                                   fld<COMP>(P, LP, off(x + ex, y + ey, z + ez)));
+                lap += d->w2[a] * (fld<COMP>(P, LP, off(x - 2 * ex, y - 2 * ey, z - 2 * ez)) +
+                                   fld<COMP>(P, LP, off(x + 2 * ex, y + 2 * ey, z + 2 * ez)));
             }
             acc[DIAG_SUM_PHI] += p;
             acc[DIAG_SUM_PHI2] += p * p;

@@ -11,7 +11,8 @@
 //   and three elements.  The row pitch
 //   sy is nx+4 rounded up to a 128-byte multiple of cells and cell (0, y, z)
 //   starts a 128-byte line.  The 2-cell halo (the zero boundary condition) is
-//   zeroed once at creation and never written afterwards.
+//   zeroed once at creation and never written afterwards; periodic solves
+//   never read it (their neighbour indices wrap into the interior).
 #pragma once
 
 #include <stdint.h>
@@ -32,7 +33,7 @@ struct SolveDesc {
     long long sy, sz;    // row and plane pitch in cells
     int nx, ny, nz, prec;
     int cs;              // elements per cell: 1 (separate fields), 2 or 4 (whole-step state slot)
-    int pad0_;
+    int periodic;        // 1: periodic boundaries (whole-step kernel and diagnostics), 0: zero halo
     double w0;           // -5/2 (1/hx^2 + 1/hy^2 + 1/hz^2)
     double w1[3];        // 4/3 / h_d^2
     double w2[3];        // -1/12 / h_d^2
@@ -69,8 +70,10 @@ struct StepShape {
     int rx, ry, blocks_per_cu;
 };
 constexpr StepShape STEP_SHAPES[3] = {{36, 28, 1}, {64, 16, 1}, {68, 15, 1}};
+// periodic: some solve of the launch has periodic boundaries (selects the
+// kernel that reads each descriptor's boundary; else the zero-halo kernel)
 int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
-                long long kstep, void* stream);
+                long long kstep, bool periodic, void* stream);
 int launch_tick(SolveDesc* descs, int count, long long k, void* stream);
 int launch_set_target(SolveDesc* descs, int index, long long target, void* stream);
 int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long target, void* stream);

@@ -111,6 +111,12 @@ __device__ __forceinline__ pair_t<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t o
         return __builtin_bit_cast(pair_t<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
+// i modulo n in [0, n) (periodic boundaries; i is at most a few cells outside)
+__device__ __forceinline__ int wrap_index(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
 // An FP32c cell (phi hi, psi hi, phi lo, psi lo) in one 16-byte access.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -598,8 +604,9 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 //
 // Every shape runs 4 waves per SIMD (the second launch-bounds argument is the
 // minimum waves per SIMD, which caps registers at 128): 16-wave blocks, one
-// per CU.
-template <typename T, bool COMP, int SK_RX, int SK_RY>
+// per CU.  PBC: the launch may hold periodic solves (each follows its own
+// descriptor); without it the kernel is the zero-halo one alone.
+template <typename T, bool COMP, int SK_RX, int SK_RY, bool PBC>
 __global__ void __launch_bounds__(SK_RX * SK_RY, 4)
 step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
             long long kstep) {
@@ -636,15 +643,20 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const bool col_int = (gx >= 0) && (gx < nx) && (gy >= 0) && (gy < ny);
     const bool core = (rx >= 2) && (rx < SK_RX - 2) && (ry >= 2) && (ry < SK_RY - 2);
     const bool own_st = core && col_int;
+    // periodic boundaries: every region column and plane is a (wrapped) grid
+    // point, so stages 1+2 run on all of them
+    const bool per = PBC && d->periodic != 0;
+    const bool col_work = per || col_int;
 
     // Loads are not predicated: a column or plane outside the stored range
     // [-2, n + 2) is clamped onto the nearest halo cell, which holds zero for
     // the life of the solve, so the loaded value is the zero the stencil
-    // needs there.  A plane is addressed through a buffer resource (scalar
+    // needs there (periodic solves: every index wraps into the interior).  A plane is addressed through a buffer resource (scalar
     // registers) and a thread's column by a 32-bit byte offset within the
     // plane, measured from the plane's cell (-2, -2); a plane is under 2 GiB.
     auto col_bytes = [&](int x, int y) -> uint32_t {
-        const int cx = min(max(x, -2), nx + 1), cy = min(max(y, -2), ny + 1);
+        const int cx = per ? wrap_index(x, nx) : min(max(x, -2), nx + 1);
+        const int cy = per ? wrap_index(y, ny) : min(max(y, -2), ny + 1);
         return (uint32_t)(((long long)(cy + 2) * sy + (cx + 2)) * (long long)CB);
     };
     const uint32_t col_b = col_bytes(gx, gy);
@@ -656,7 +668,8 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const unsigned long long bY = (unsigned long long)Y - cb, bO = (unsigned long long)O - cb;
     auto poff = [&](int p) -> unsigned long long { return (unsigned long long)((long long)p * pbytes); };
     auto rs = [&](unsigned long long b, unsigned long long off) { return plane_rsrc(b + off, pbytes); };
-    auto clampz = [&](int p) { return min(max(p, -2), nz + 1); };
+    auto clampz = [&](int p) { return per ? wrap_index(p, nz) : min(max(p, -2), nz + 1); };
+    auto zmap = [&](int p) { return per ? wrap_index(p, nz) : p; };
 
     // outer ring (R4 minus R2): rows 0,1 and QY-2,QY-1 of R4, then columns
     // 0,1 and QX-2,QX-1 of the middle rows
@@ -682,7 +695,7 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     const int z0 = tl.z0, z1 = tl.z1;
     const int zbase = z0 - 2;           // first plane of stages 1+2
     const int niter = z1 - z0 + 4;      // planes zbase .. z1+1 carry work
-    const int zlast = min(z1 + 3, nz + 1);  // highest plane a needed evaluation reads
+    const int zlast = per ? z1 + 3 : min(z1 + 3, nz + 1);  // highest plane a needed evaluation reads
 
     // rings indexed by (plane - zbase + 6) % 6 (+6: planes down to zbase-2)
     // Loads are issued at the end of a plane into the ring slot that plane
@@ -761,7 +774,7 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         __syncthreads();
 
         T g1 = T(0), g2 = T(0);
-        if (col_int && zi >= 0 && zi < nz) {
+        if (col_work && (per || (zi >= 0 && zi < nz))) {
             const int lx = rx + 2, ly = ry + 2;
             const T(*A)[SK_QX] = pa[B];
             const T(*Bp)[SK_QX] = pb[B];
@@ -845,10 +858,10 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         // clamped and the value is never used)
         // own plane zi+4 into the slot of plane zi-2 (last used just above);
         // zi+4 >= z0+2 >= 2, and planes past nz+1 are never needed
-        ld_own_slot(Q(4), min(zi + 4, zlast));
+        ld_own_slot(Q(4), zmap(min(zi + 4, zlast)));
         // outer plane zi+3 into the slot of plane zi (used before the barrier);
         // the stencil needs only (phi, psi) (FP32c: the high parts)
-        const pair_t<T> v3 = bload2<T>(rs(bY, poff(min(zi + 3, z1 + 1))), outer_b);
+        const pair_t<T> v3 = bload2<T>(rs(bY, poff(zmap(min(zi + 3, z1 + 1)))), outer_b);
         opr[OS] = v3.x;
         osr[OS] = v3.y;
     };
@@ -989,23 +1002,27 @@ hipError_t launch_pair_t(int pair, const SolveDesc* descs, const Tile* tiles, in
 
 template <typename T, bool COMP, int RX, int RY>
 hipError_t launch_step_shape(const SolveDesc* descs, const Tile* tiles, int ntiles, long long kstep,
-                             hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<T, COMP, RX, RY>), dim3(ntiles), dim3(RX * RY), 0, s, descs,
-                       tiles, ntiles, kstep);
+                             bool pbc, hipStream_t s) {
+    if (pbc)
+        hipLaunchKernelGGL((step_kernel<T, COMP, RX, RY, true>), dim3(ntiles), dim3(RX * RY), 0, s,
+                           descs, tiles, ntiles, kstep);
+    else
+        hipLaunchKernelGGL((step_kernel<T, COMP, RX, RY, false>), dim3(ntiles), dim3(RX * RY), 0, s,
+                           descs, tiles, ntiles, kstep);
     return hipGetLastError();
 }
 
 // region shapes, indexed as STEP_SHAPES in hb_internal.h
 template <typename T, bool COMP>
 hipError_t launch_step_t(int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
-                         long long kstep, hipStream_t s) {
+                         long long kstep, bool pbc, hipStream_t s) {
     static_assert(STEP_SHAPES[0].rx == 36 && STEP_SHAPES[0].ry == 28, "shape table");
     static_assert(STEP_SHAPES[1].rx == 64 && STEP_SHAPES[1].ry == 16, "shape table");
     static_assert(STEP_SHAPES[2].rx == 68 && STEP_SHAPES[2].ry == 15, "shape table");
     switch (shape) {
-        case 0: return launch_step_shape<T, COMP, 36, 28>(descs, tiles, ntiles, kstep, s);
-        case 1: return launch_step_shape<T, COMP, 64, 16>(descs, tiles, ntiles, kstep, s);
-        case 2: return launch_step_shape<T, COMP, 68, 15>(descs, tiles, ntiles, kstep, s);
+        case 0: return launch_step_shape<T, COMP, 36, 28>(descs, tiles, ntiles, kstep, pbc, s);
+        case 1: return launch_step_shape<T, COMP, 64, 16>(descs, tiles, ntiles, kstep, pbc, s);
+        case 2: return launch_step_shape<T, COMP, 68, 15>(descs, tiles, ntiles, kstep, pbc, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1048,12 +1065,12 @@ int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* 
 }
 
 int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,
-                long long kstep, void* stream) {
+                long long kstep, bool periodic, void* stream) {
     if (ntiles <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = prec == PREC_F64
-                       ? launch_step_t<double, false>(shape, descs, tiles, ntiles, kstep, s)
-                       : launch_step_t<float, true>(shape, descs, tiles, ntiles, kstep, s);
+                       ? launch_step_t<double, false>(shape, descs, tiles, ntiles, kstep, periodic, s)
+                       : launch_step_t<float, true>(shape, descs, tiles, ntiles, kstep, periodic, s);
     return (int)e;
 }
 

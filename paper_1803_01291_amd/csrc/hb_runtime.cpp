@@ -214,6 +214,8 @@ int validate(const hb_config* c) {
     if (!(c->dt > 0) || !std::isfinite(c->dt)) return fail(HB_E_ARG, "dt must be > 0");
     if (c->inv_L2 < 0) return fail(HB_E_ARG, "inv_L2 must be >= 0");
     if (c->precision != HB_F64 && c->precision != HB_F32C) return fail(HB_E_ARG, "bad precision");
+    if ((c->flags & HB_BC_PERIODIC) && scheme_of(c->flags) != SCHEME_STEP)
+        return fail(HB_E_ARG, "periodic boundaries need the whole-step scheme");
     if (scheme_of(c->flags) == SCHEME_STEP) {
         // the whole-step kernel addresses a plane with 32-bit byte offsets
         const Layout L = plan_layout(*c, SCHEME_STEP);
@@ -361,6 +363,7 @@ SolveDesc make_desc(const Solve& s) {
     d.sy = s.L.sy;
     d.sz = s.L.sz;
     d.cs = s.L.cs;
+    d.periodic = (s.cfg.flags & HB_BC_PERIODIC) ? 1 : 0;
     d.nx = s.L.nx;
     d.ny = s.L.ny;
     d.nz = s.L.nz;
@@ -474,6 +477,7 @@ struct Group {
     Tile* d_tiles = nullptr;
     int tile_cap = 0;
     int ntiles = 0;
+    bool periodic = false;  // some member has periodic boundaries
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_k = 0;
@@ -615,6 +619,8 @@ int group_rebuild(Group& g, hipStream_t stream) {
     if (!tiles.empty())
         HIP_TRY(hipMemcpy(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
     g.ntiles = (int)tiles.size();
+    g.periodic = false;
+    for (Solve* m : g.members) g.periodic = g.periodic || (m->cfg.flags & HB_BC_PERIODIC);
     return HB_OK;
 }
 
@@ -626,7 +632,7 @@ int kernels_per_step(const Group& g) {
 int launch_step_kernel(const Group& g, int i, long long kstep, hipStream_t stream) {
     if (g.scheme == SCHEME_STEP)
         return from_hip(launch_step(g.prec, step_shape(g.by), g.d_desc, g.d_tiles, g.ntiles, kstep,
-                                    stream),
+                                    g.periodic, stream),
                         "step launch");
     if (g.scheme == SCHEME_STAGES)
         return from_hip(launch_stage(g.prec, i + 1, g.by, g.d_desc, g.d_tiles, g.ntiles, kstep, stream),

@@ -119,3 +119,13 @@ def test_allocator_hook_arguments(lib):
     assert lib.hb_set_allocator(None, None, None) == hb.HB_OK
     with pytest.raises(ValueError):
         hb.hb_set_allocator(lambda n, s: 0, None)
+
+
+def test_periodic_flag_needs_the_whole_step_scheme(lib):
+    """HB_BC_PERIODIC is validated on the host: the whole-step scheme accepts
+    it, the stage-pair and per-stage schemes do not (footprint 0 = invalid)."""
+    from paper_1803_01291_amd import hb
+    base = dict(n=(32, 16, 8), lo=(0.0,) * 3, hi=(8.0, 4.0, 2.0), mu2=2.0, lam=1.0, dt=0.01)
+    assert hb.hb_footprint(hb.make_config(**base, flags=hb.HB_BC_PERIODIC)) > 0
+    for f in (hb.HB_PAIRWISE, hb.HB_STAGEWISE):
+        assert hb.hb_footprint(hb.make_config(**base, flags=hb.HB_BC_PERIODIC | f)) == 0
