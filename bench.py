@@ -35,6 +35,9 @@ Prints ONE JSON line.  Extra objects:
                    default grid, 500^3 cells, dt = 1e-4, FP64 and FP32c: step
                    rate and the projected hours to t = 50 (5e5 steps) beside
                    the paper's 27 h;
+  accuracy      -- after the workload's 2000 steps, FP64 and FP32c: relative
+                   max error at the oracle's stored sample nodes, and FP32c
+                   against FP64 over the whole grid (max and L2);
   paper_context -- the paper's own K40c rate (context, not a baseline).
 """
 import argparse
@@ -256,6 +259,52 @@ def run_radial(count, m, steps, cpu_sample):
             "cpu_baseline": cpu}
 
 
+def run_accuracy(w):
+    """Errors of the benchmark workload after its 2000 steps, FP64 and FP32c
+    from the same initial data: against the oracle's values at the sampled
+    nodes stored by tests/golden/make_golden.py (relative to the oracle's
+    whole-grid max norm), and FP32c against FP64 over the whole grid (max
+    and L2, relative)."""
+    import numpy as np
+    from paper_1803_01291_amd import hb
+    path = os.path.join(ROOT, "tests", "golden", "cube256_gauss8_oracle.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    if list(w.n) != g["n"] or w.dt != g["dt"] or w.mu2 != g["mu2"]:
+        return None
+    steps = g["steps"]
+    p0, p1 = w.initial()
+    out = {}
+    for prec in (0, 1):
+        h = hb.hb_create(hb.config_from_workload(w, prec))
+        try:
+            hb.hb_set_initial(h, p0, p1)
+            hb.hb_step(h, steps)
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_read(h, phi, psi)
+        finally:
+            hb.hb_destroy(h)
+        out[prec] = (phi, psi)
+    pts = np.array(g["points_zyx"])
+    idx = (pts[:, 0], pts[:, 1], pts[:, 2])
+    den = max(g["max_abs_phi"], g["max_abs_psi"])
+
+    def sampled(phi, psi):
+        return max(np.max(np.abs(phi[idx] - np.array(g["phi"]))),
+                   np.max(np.abs(psi[idx] - np.array(g["psi"])))) / den
+
+    (a, b), (c, d) = out[0], out[1]
+    den64 = max(np.max(np.abs(a)), np.max(np.abs(b)))
+    l2 = np.sqrt(np.sum((c - a) ** 2) + np.sum((d - b) ** 2))
+    l2ref = np.sqrt(np.sum(a ** 2) + np.sum(b ** 2))
+    return {"steps": steps, "oracle_nodes": len(pts),
+            "f64_vs_oracle_sampled_rel_max": float(sampled(a, b)),
+            "f32c_vs_oracle_sampled_rel_max": float(sampled(c, d)),
+            "f32c_vs_f64_rel_max": float(max(np.max(np.abs(c - a)), np.max(np.abs(d - b))) / den64),
+            "f32c_vs_f64_rel_l2": float(l2 / l2ref)}
+
+
 def cpu_baseline(w, steps):
     import oracle
     p0, p1 = w.initial()
@@ -289,6 +338,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-radial", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the error check of the workload against the stored oracle samples")
     ap.add_argument("--no-paper-grid", action="store_true",
                     help="skip the paper's default-grid leg (Example 7, 500^3, dt 1e-4)")
     ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
@@ -391,6 +442,8 @@ def main():
             print(f"serve sweep: {rate} req/s: p50 {r['p50_latency_s']:.3f} s, "
                   f"p99 {r['p99_latency_s']:.3f} s, {r['solves_per_s']:.2f} solves/s",
                   file=sys.stderr, flush=True)
+    if not args.no_accuracy and args.n == 256:
+        out["accuracy"] = run_accuracy(w)
     if not args.no_shard:
         out["shard"] = run_shard(200, 10)
     if not args.no_paper_grid:
