@@ -72,6 +72,11 @@ extern "C" {
 #define HB_PAIRWISE 8u       /* one launch per stage pair (10 passes per step) */
                              /* instead of the default whole-step launch (4   */
                              /* passes); bitwise-equal results                */
+#define HB_DEBUG_POISON 32u  /* debug: fill every stored cell outside the     */
+                             /* interior and its 2-cell halo (pitch padding,  */
+                             /* alignment prefix, tail) with quiet NaNs at    */
+                             /* creation, so a kernel reading one would carry */
+                             /* NaN into the results; results are unchanged   */
 #define HB_BC_PERIODIC 16u   /* periodic boundaries on every axis instead of  */
                              /* the zero 2-cell halo (a test configuration:   */
                              /* e.g. constant data then follows the damped    */

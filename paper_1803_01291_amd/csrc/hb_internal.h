@@ -81,6 +81,11 @@ int launch_set_nstep(SolveDesc* descs, int index, long long nstep, long long tar
 // Contiguous user array [nz][ny][nx] of src_dtype (0 = f64, 1 = f32) into a
 // pitched field (cs elements per cell).  FP64 fields take the value; FP32c fields take
 // hi = (float)v and lo = (float)(v - hi).  `src` may be NULL for zeros.
+// quiet NaNs into every cell of one field (field start address, `cells`
+// cells of cs elements of esz bytes) outside the interior and its 2-cell
+// halo; corner = cell index of (-2, -2, -2), sz = sy * (ny + 4)
+int launch_poison(void* field, long long cells, int esz, int cs, long long corner, long long sy,
+                  long long sz, int nx, int nz, void* stream);
 int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,
                   long long sz, int cs, void* hi, float* lo, void* stream);
 // Pitched field into a contiguous user array of dst_dtype (FP32c: hi + lo in FP64).

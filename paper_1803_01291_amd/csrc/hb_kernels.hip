@@ -906,6 +906,31 @@ __global__ void set_nstep_kernel(SolveDesc* descs, int i, long long nstep, long 
     }
 }
 
+// Debug layout check: every cell of a field that is neither interior nor in
+// the 2-cell halo (row-pitch padding, the line-alignment prefix, the tail)
+// gets quiet NaNs in all its elements, so a kernel that read one would carry
+// NaN into its results.  `corner` is the cell index of (-2, -2, -2).
+__global__ void poison_kernel(unsigned char* __restrict__ field, long long cells, int esz, int cs,
+                              long long corner, long long sy, long long sz, int nx, int nz) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += stride) {
+        const long long r = i - corner;
+        bool keep = false;
+        if (r >= 0) {
+            const long long zz = r / sz, xx = (r - zz * sz) % sy;  // rows of a plane are all kept
+            keep = xx < nx + 4 && zz < nz + 4;
+        }
+        if (keep) continue;
+        for (int e = 0; e < cs; ++e) {
+            unsigned char* p = field + (i * cs + e) * esz;
+            if (esz == 8)
+                *(unsigned long long*)p = 0x7ff8000000000000ull;
+            else
+                *(unsigned int*)p = 0x7fc00000u;
+        }
+    }
+}
+
 template <typename S, bool COMP>
 __global__ void unpack_kernel(const S* __restrict__ src, int nx, int ny, int nz, long long sy,
                               long long sz, int cs, void* __restrict__ hi, float* __restrict__ lo) {
@@ -1097,6 +1122,13 @@ static unsigned grid_for(long long total) {
     long long blocks = (total + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+int launch_poison(void* field, long long cells, int esz, int cs, long long corner, long long sy,
+                  long long sz, int nx, int nz, void* stream) {
+    hipLaunchKernelGGL(poison_kernel, dim3(grid_for(cells)), dim3(256), 0, (hipStream_t)stream,
+                       (unsigned char*)field, cells, esz, cs, corner, sy, sz, nx, nz);
+    return (int)hipGetLastError();
 }
 
 int launch_unpack(int prec, int src_dtype, const void* src, int nx, int ny, int nz, long long sy,

@@ -290,6 +290,13 @@ int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
     HB_TRY(dev_alloc((void**)&s.mem, total, "solve state", stream));
     // zero everything once: the halo stays zero for the life of the solve
     HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
+    if (c.flags & HB_DEBUG_POISON) {
+        const long long corner = s.L.origin_off - 2 * s.L.sz - 2 * s.L.sy - 2;
+        for (int k = 0; k < s.L.nfields; ++k)
+            HB_TRY(from_hip(launch_poison(s.mem + fb * (size_t)k, s.L.field_cells, (int)s.L.esz, s.L.cs,
+                                          corner, s.L.sy, s.L.sz, s.L.nx, s.L.nz, stream),
+                            "poison"));
+    }
     const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
     if (s.L.cs > 1) {
         for (int par = 0; par < 2; ++par) {

@@ -24,6 +24,7 @@ HB_F64, HB_F32C = 0, 1
 HB_HOST, HB_DEVICE = 0, 1
 HB_DTYPE_F64, HB_DTYPE_F32 = 0, 1
 HB_ALLOW_UNSTABLE, HB_USE_GRAPH, HB_STAGEWISE, HB_PAIRWISE, HB_BC_PERIODIC = 1, 2, 4, 8, 16
+HB_DEBUG_POISON = 32
 
 _NAMES = {HB_E_ARG: "HB_E_ARG", HB_E_CFL: "HB_E_CFL", HB_E_NOMEM: "HB_E_NOMEM",
           HB_E_HIP: "HB_E_HIP", HB_E_STATE: "HB_E_STATE", HB_E_BUSY: "HB_E_BUSY",

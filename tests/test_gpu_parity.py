@@ -322,3 +322,78 @@ def test_random_configurations(hb, oracle_mod, case):
     err = oracle.rel_maxnorm(*g, *r)
     print(f"case {case}: rel err {err:.3e}")
     assert err <= (TOL32C if prec else TOL64)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32c"])
+@pytest.mark.parametrize("flags", ["step", "HB_PAIRWISE", "HB_STAGEWISE", "HB_BC_PERIODIC"])
+def test_padding_is_never_read(hb, prec, flags):
+    """HB_DEBUG_POISON fills every stored cell outside the interior and its
+    2-cell halo with NaN: no kernel reads one, so results stay bitwise those
+    of a clean run and the diagnostics find no NaN."""
+    f = 0 if flags == "step" else getattr(hb, flags)
+    wide = (11, 6) if f in (0, hb.HB_BC_PERIODIC) else (16, 6)
+    for shape, tiling in [((70, 21, 13), None), ((5, 3, 7), (8, 0)), ((130, 25, 19), wide),
+                          ((1, 2, 6), None)]:
+        w = si.small_case(*shape, seed=sum(shape) + 3, steps=5)
+        clean = run_gpu(hb, w, precision=prec, flags=f, tiling=tiling)
+        p0, p1 = w.initial()
+        h = hb.hb_create(hb.config_from_workload(w, prec, f | hb.HB_DEBUG_POISON))
+        try:
+            if tiling is not None:
+                hb.hb_set_tiling(h, *tiling)
+            hb.hb_set_initial(h, p0, p1)
+            hb.hb_step(h, w.steps)
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_read(h, phi, psi)
+            d = hb.hb_diagnostics(h)
+        finally:
+            hb.hb_destroy(h)
+        np.testing.assert_array_equal(phi, clean[0])
+        np.testing.assert_array_equal(psi, clean[1])
+        assert d["nonfinite"] == 0
+
+
+def test_poison_marks_exactly_the_padding(hb):
+    """The check above is not vacuous: the raw state allocation of a poisoned
+    whole-step solve (caught through the allocator hook) holds NaN in every
+    cell outside the interior and its halo, and zeros in the rest."""
+    import torch
+    held = {}
+
+    def alloc(nbytes, stream):
+        t = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        held[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def release(ptr, nbytes):
+        held.pop(ptr)
+
+    nx, ny, nz = 13, 9, 5
+    w = si.small_case(nx, ny, nz, seed=1, steps=1)
+    hb.hb_set_allocator(alloc, release)
+    try:
+        h = hb.hb_create(hb.config_from_workload(w, 0, hb.HB_DEBUG_POISON))
+    finally:
+        hb.hb_set_allocator()
+    try:
+        hb.hb_sync(h)
+        # layout of the whole-step state: 16-byte cells, 8 to a 128-byte line,
+        # row pitch nx + 4 rounded up to a line, cell (0, y, z) on a line,
+        # fields rounded up to 256 bytes, one field per step parity
+        ru = lambda v, m: (v + m - 1) // m * m
+        sy = ru(nx + 4, 8)
+        sz = sy * (ny + 4)
+        origin = 2 * sz + 2 * sy + 8
+        cells = ru(origin + (nz + 1) * sz + (ny + 1) * sy + nx + 2, 16)
+        state = [t for t in held.values() if t.numel() == 2 * cells * 16]
+        assert len(state) == 1
+        raw = state[0].cpu().numpy().view(np.float64).reshape(2, cells, 2)
+    finally:
+        hb.hb_destroy(h)
+    keep = np.zeros(cells, bool)
+    for z in range(-2, nz + 2):
+        for y in range(-2, ny + 2):
+            keep[origin + z * sz + y * sy + np.arange(-2, nx + 2)] = True
+    assert np.isnan(raw[:, ~keep, :]).all()
+    assert (raw[:, keep, :] == 0).all()
+    assert held == {}
