@@ -38,7 +38,8 @@ Prints ONE JSON line.  Extra objects:
   accuracy      -- after the workload's 2000 steps, FP64 and FP32c: relative
                    max error at the oracle's stored sample nodes, and FP32c
                    against FP64 over the whole grid (max and L2);
-  paper_context -- the paper's own K40c rate (context, not a baseline).
+  paper_context -- the paper's own K40c rate (context, not a baseline);
+  system        -- device name, CUs, HBM, host CPU count and model.
 """
 import argparse
 import json
@@ -70,9 +71,9 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "a214fc3757315e8a"
+TRAFFIC_SOURCE_SHA = "ceccc0b1920df933"
 TRAFFIC_KERNEL = "step_kernel<double, false, 68, 15, false>"  # the 256^3 default region shape
-TRAFFIC_BYTES_F64 = 611.3 * 2 ** 20
+TRAFFIC_BYTES_F64 = 611.4 * 2 ** 20
 
 
 def source_sha():
@@ -259,6 +260,22 @@ def run_radial(count, m, steps, cpu_sample):
             "cpu_baseline": cpu}
 
 
+def system_info():
+    """The device and host the run used."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"device": p.name, "arch": getattr(p, "gcnArchName", ""), "cus": p.multi_processor_count,
+            "hbm_GiB": round(p.total_memory / 2 ** 30, 1), "host_cpus": os.cpu_count(), "host_cpu": cpu}
+
+
 def run_accuracy(w):
     """Errors of the benchmark workload after its 2000 steps, FP64 and FP32c
     from the same initial data: against the oracle's values at the sampled
@@ -442,6 +459,7 @@ def main():
             print(f"serve sweep: {rate} req/s: p50 {r['p50_latency_s']:.3f} s, "
                   f"p99 {r['p99_latency_s']:.3f} s, {r['solves_per_s']:.2f} solves/s",
                   file=sys.stderr, flush=True)
+    out["system"] = system_info()
     if not args.no_accuracy and args.n == 256:
         out["accuracy"] = run_accuracy(w)
     if not args.no_shard:

@@ -139,7 +139,9 @@ int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int 
  * Each step is one whole-step kernel (default), 2 stage-pair kernels
  * (HB_PAIRWISE) or 4 per-stage kernels (HB_STAGEWISE); a tiny kernel advances
  * the device step counter after each batch of steps.  HB_E_STATE before
- * initial data. */
+ * initial data.  With HB_TRACE set in the environment (and not "0") every
+ * kernel is timed with HIP events and waited for, and each step prints one
+ * line with the kernels' times to stderr. */
 int hb_step(hb_solver* s, int64_t nsteps);
 
 /* Like hb_step, but waits after every step and returns the summed device time

@@ -828,6 +828,16 @@ int hb_set_initial(hb_solver* h, const void* phi0, const void* phi1, int mem, in
     return hb_set_state(h, phi0, phi1, 0, mem, dtype);
 }
 
+// HB_TRACE set (and not "0") in the environment: hb_step times every kernel
+// launch with events, waits for it, and prints one line per step to stderr
+static bool trace_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("HB_TRACE");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
 int hb_step(hb_solver* h, int64_t nsteps) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
     if (nsteps < 0 || nsteps > MAX_STEPS) return fail(HB_E_ARG, "nsteps must be in [0, 2^40]");
@@ -837,6 +847,17 @@ int hb_step(hb_solver* h, int64_t nsteps) {
     HB_TRY(set_targets(h->g, nsteps, h->stream, &moved));
     if (moved || !h->built) HB_TRY(solver_rebuild(h));
     HB_TRY(from_hip(launch_set_target(h->g.d_desc, 0, h->s->target, h->stream), "set target"));
+    if (trace_enabled()) {
+        const int nk = kernels_per_step(h->g);
+        for (long long j = 0; j < nsteps; ++j) {
+            double ms[4];
+            HB_TRY(group_step_timed(h->g, 1, h->stream, ms));
+            std::fprintf(stderr, "hb_trace solver %p step %lld:", (void*)h, h->s->nstep);
+            for (int k = 0; k < nk; ++k) std::fprintf(stderr, " %.4f ms", ms[k]);
+            std::fprintf(stderr, "\n");
+        }
+        return HB_OK;
+    }
     return group_step(h->g, nsteps, (h->s->cfg.flags & HB_USE_GRAPH) != 0, h->stream);
 }
 

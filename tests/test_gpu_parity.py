@@ -397,3 +397,24 @@ def test_poison_marks_exactly_the_padding(hb):
     assert np.isnan(raw[:, ~keep, :]).all()
     assert (raw[:, keep, :] == 0).all()
     assert held == {}
+
+
+def test_trace_prints_one_line_per_step():
+    """HB_TRACE=1: hb_step times each launch and prints a line per step (run
+    in a child process, since the setting is read once per process)."""
+    import os
+    import subprocess
+    import sys
+    code = ("import synth_inputs as si\n"
+            "from paper_1803_01291_amd import hb\n"
+            "w = si.small_case(40, 20, 10, seed=5, steps=3)\n"
+            "hb.solve_host(w)\n"
+            "hb.solve_host(w, flags=hb.HB_PAIRWISE)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, HB_TRACE="1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=240, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("hb_trace")]
+    assert len(lines) == 6
+    assert all(l.count(" ms") == 1 for l in lines[:3]) and all(l.count(" ms") == 2 for l in lines[3:])
