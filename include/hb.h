@@ -250,6 +250,14 @@ int hb_pool_advance(hb_pool* p, int k);
  * reported once. */
 int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone);
 
+/* Check every active solve for non-finite values (NaN or Inf in phi or psi;
+ * one FP64 diagnostics pass over each, so call it every so many advances):
+ * a solve that holds any stops stepping, its slot is written to
+ * failed[0 .. cap-1] (*nfailed = the number written) and hb_pool_poll then
+ * reports it as finished (its state can still be read); the other solves
+ * continue unchanged.  Waits for the pool's stream. */
+int hb_pool_check(hb_pool* p, int* failed, int cap, int* nfailed);
+
 /* Number of admitted, unfinished solves and bytes of the budget in use. */
 int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use);
 

@@ -1366,6 +1366,60 @@ int hb_pool_poll(hb_pool* p, int* done, int cap, int* ndone) {
     return HB_OK;
 }
 
+int hb_pool_check(hb_pool* p, int* failed, int cap, int* nfailed) {
+    if (!p || !nfailed || (cap > 0 && !failed)) return fail(HB_E_ARG, "NULL argument");
+    *nfailed = 0;
+    if (p->dirty) HB_TRY(pool_rebuild(p));
+    // one diagnostics pass per active solve, on its group's descriptor; the
+    // partials buffer is reused in stream order
+    int maxparts = 0, members = 0;
+    for (Group& g : p->groups)
+        for (Solve* s : g.members) {
+            maxparts = std::max(maxparts, diag_partials_needed(s->L.nx, s->L.ny, s->L.nz));
+            ++members;
+        }
+    if (members == 0) return HB_OK;
+    double* parts = nullptr;
+    double* outs = nullptr;
+    HB_TRY(dev_alloc((void**)&parts, (size_t)maxparts * DIAG_COUNT * sizeof(double), "check partials",
+                     p->stream));
+    int rc = dev_alloc((void**)&outs, (size_t)members * DIAG_COUNT * sizeof(double), "check results",
+                       p->stream);
+    std::vector<double> host((size_t)members * DIAG_COUNT);
+    std::vector<Solve*> order;
+    for (Group& g : p->groups)
+        for (size_t i = 0; i < g.members.size() && rc == HB_OK; ++i) {
+            Solve* s = g.members[i];
+            rc = from_hip(launch_diagnostics(s->prec(), g.d_desc + i, (int)(s->nstep & 1), 0.0, parts,
+                                             diag_partials_needed(s->L.nx, s->L.ny, s->L.nz),
+                                             outs + order.size() * DIAG_COUNT, p->stream),
+                          "check");
+            order.push_back(s);
+        }
+    if (rc == HB_OK)
+        rc = from_hip(hipMemcpyAsync(host.data(), outs, host.size() * sizeof(double),
+                                     hipMemcpyDeviceToHost, p->stream),
+                      "check copy");
+    if (rc == HB_OK) rc = from_hip(hipStreamSynchronize(p->stream), "check sync");
+    dev_free(parts);
+    dev_free(outs);
+    HB_TRY(rc);
+    int n = 0;
+    for (size_t m = 0; m < order.size(); ++m) {
+        if (host[m * DIAG_COUNT + DIAG_NONFINITE] == 0.0) continue;
+        for (size_t i = 0; i < p->slots.size(); ++i) {
+            auto& sl = p->slots[i];
+            if (!sl.busy || sl.s.get() != order[m]) continue;
+            sl.done = true;  // stops stepping; hb_pool_poll reports it
+            p->dirty = true;
+            if (n < cap) failed[n] = (int)i;
+            ++n;
+        }
+    }
+    *nfailed = std::min(n, std::max(cap, 0));
+    return HB_OK;
+}
+
 int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use) {
     if (!p) return fail(HB_E_ARG, "pool is NULL");
     int a = 0;

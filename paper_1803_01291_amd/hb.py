@@ -96,6 +96,7 @@ _SIGS = {
     "hb_pool_admit": [_P, ctypes.POINTER(hb_config), _P, _P, _I, _I, _I64, ctypes.POINTER(_I)],
     "hb_pool_advance": [_P, _I],
     "hb_pool_poll": [_P, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)],
+    "hb_pool_check": [_P, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)],
     "hb_pool_stats": [_P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_size_t)],
     "hb_pool_read": [_P, _I, _P, _P, _I, _I],
     "hb_pool_release": [_P, _I],
@@ -423,6 +424,14 @@ def hb_pool_poll(p: int, cap: int = 1024):
     buf = (_I * cap)()
     n = _I()
     _check(load().hb_pool_poll(p, buf, cap, ctypes.byref(n)))
+    return list(buf[: n.value])
+
+
+def hb_pool_check(p: int, cap: int = 1024):
+    """Slots whose state holds NaN/Inf; they stop stepping (see include/hb.h)."""
+    buf = (_I * cap)()
+    n = _I()
+    _check(load().hb_pool_check(p, buf, cap, ctypes.byref(n)))
     return list(buf[: n.value])
 
 

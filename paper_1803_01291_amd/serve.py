@@ -42,6 +42,7 @@ class Completion:
     done: float
     phi: np.ndarray
     psi: np.ndarray
+    failed: bool = False       # its state turned non-finite (stopped early)
 
     @property
     def latency(self) -> float:
@@ -49,9 +50,12 @@ class Completion:
 
 
 def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advance_k: int = 25,
-          lookahead: int = 8, keep_results: bool = True,
+          lookahead: int = 8, keep_results: bool = True, check_every: int = 0,
           clock: Callable[[], float] = time.perf_counter) -> Dict:
-    """Run the request stream to completion; returns completions and stats."""
+    """Run the request stream to completion; returns completions and stats.
+    With ``check_every`` > 0 the pool is checked for non-finite states every
+    that many advances; such a solve stops, completes with ``failed`` set,
+    and the others continue."""
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue: collections.deque = collections.deque()
     pool = hb.hb_pool_create(budget_bytes, max_slots)
@@ -59,6 +63,7 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
     done: List[Completion] = []
     advances = 0
     max_active = 0
+    failed_slots = set()
     t0 = clock()
     try:
         while pending or queue or inflight:
@@ -86,6 +91,8 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
                 break
             hb.hb_pool_advance(pool, advance_k)
             advances += 1
+            if check_every and advances % check_every == 0:
+                failed_slots.update(hb.hb_pool_check(pool))
             active, _ = hb.hb_pool_stats(pool)
             max_active = max(max_active, active)
             for slot in hb.hb_pool_poll(pool):
@@ -97,7 +104,9 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
                 hb.hb_pool_release(pool, slot)
                 t_done = clock() - t0
                 done.append(Completion(r.index, r.arrival, t_adm, t_done,
-                                       phi if keep_results else None, psi if keep_results else None))
+                                       phi if keep_results else None, psi if keep_results else None,
+                                       failed=slot in failed_slots))
+                failed_slots.discard(slot)
     finally:
         hb.hb_pool_destroy(pool)
     lat = np.array([c.latency for c in done]) if done else np.zeros(1)
@@ -111,5 +120,6 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
         "pt_updates_per_s": pts / span if span > 0 else 0.0,
         "span_s": span,
         "advances": advances,
+        "failed": sum(1 for c in done if c.failed),
         "max_active": max_active,
     }

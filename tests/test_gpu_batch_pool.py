@@ -180,3 +180,43 @@ def test_serving_loop_results_equal_alone(hb):
         ref = alone(hb, ws[c.index], precs[c.index], steps[c.index])
         np.testing.assert_array_equal(c.phi, ref[0])
         np.testing.assert_array_equal(c.psi, ref[1])
+
+
+def test_pool_check_stops_nonfinite_solves_only(hb):
+    """A solve whose state turns non-finite (NaN planted in its initial data
+    on the host) is found by hb_pool_check, stops stepping and is reported by
+    poll; the other solves finish bitwise as they do alone."""
+    ws = [si.small_case(40, 24, 16, seed=s, steps=20) for s in (21, 22, 23)]
+    data = [list(w.initial()) for w in ws]
+    data[1][0] = data[1][0].copy()
+    data[1][0][5, 6, 7] = np.nan
+    pool = hb.hb_pool_create(1 << 30, 8)
+    try:
+        slots = [hb.hb_pool_admit(pool, hb.config_from_workload(w), d[0], d[1], 20)
+                 for w, d in zip(ws, data)]
+        hb.hb_pool_advance(pool, 4)
+        assert hb.hb_pool_check(pool) == [slots[1]]
+        assert hb.hb_pool_check(pool) == []           # already stopped
+        assert hb.hb_pool_stats(pool)[0] == 2
+        for _ in range(4):
+            hb.hb_pool_advance(pool, 4)
+        assert sorted(hb.hb_pool_poll(pool)) == sorted(slots)
+        for k in (0, 2):
+            phi = np.empty(ws[k].n[::-1])
+            hb.hb_pool_read(pool, slots[k], phi, None)
+            np.testing.assert_array_equal(phi, hb.solve_host(ws[k], 20)[0])
+    finally:
+        hb.hb_pool_destroy(pool)
+
+
+def test_serving_loop_reports_failed_requests(hb):
+    from paper_1803_01291_amd.serve import Request, serve
+    ws = [si.small_case(32, 16, 12, seed=s, steps=30) for s in (31, 32)]
+    bad = ws[1].initial()[0].copy()
+    bad[2, 3, 4] = np.inf
+    reqs = [Request(0, 0.0, hb.config_from_workload(ws[0]), 30, *ws[0].initial()),
+            Request(1, 0.0, hb.config_from_workload(ws[1]), 30, bad, ws[1].initial()[1])]
+    out = serve(reqs, 1 << 30, advance_k=5, check_every=1)
+    by_index = {c.index: c for c in out["completions"]}
+    assert out["failed"] == 1 and by_index[1].failed and not by_index[0].failed
+    np.testing.assert_array_equal(by_index[0].phi, hb.solve_host(ws[0], 30)[0])
