@@ -92,7 +92,7 @@ typedef struct hb_config {
     double dt;           /* RK4 time step (> 0)                                     */
     int32_t precision;   /* HB_F64 or HB_F32C                                       */
     uint32_t flags;      /* HB_ALLOW_UNSTABLE | HB_USE_GRAPH | HB_PAIRWISE |        */
-                         /* HB_STAGEWISE                                            */
+                         /* HB_STAGEWISE | HB_DEBUG_POISON | HB_BC_PERIODIC         */
     void* stream;        /* hipStream_t to order work on, or NULL                   */
 } hb_config;
 
@@ -122,6 +122,8 @@ typedef struct hb_pool hb_pool;
  * The stability check requires dt * sqrt(c0 * sum_d 16/(3 h_d^2)) <= 2 sqrt(2),
  * c0 = inv_L2 exp(-2 t0) (RK4's imaginary-axis limit against the largest
  * eigenvalue of -Lap_h); HB_E_CFL otherwise unless HB_ALLOW_UNSTABLE.
+ * Whole-step solves (the default) need an x-y plane of 16-byte cells under
+ * 2 GiB (up to 11580^2 points); larger planes are HB_E_ARG.
  * Errors: HB_E_ARG, HB_E_CFL, HB_E_NOMEM, HB_E_HIP.  *out is NULL on error. */
 int hb_create(const hb_config* cfg, hb_solver** out);
 
@@ -132,7 +134,9 @@ int hb_create(const hb_config* cfg, hb_solver** out);
  * returns; device inputs are read in stream order. */
 int hb_set_initial(hb_solver* s, const void* phi0, const void* phi1, int mem, int dtype);
 
-/* Restore a checkpoint: state (phi, psi) at step n (t = t0 + n dt). */
+/* Restore a checkpoint: state (phi, psi) at step n (t = t0 + n dt), 0 <= n
+ * <= 2^40; psi may be NULL for zero.  Stepping on from it is bitwise the same
+ * as never having stopped. */
 int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int mem, int dtype);
 
 /* Enqueue nsteps RK4 steps on the solver's stream and return without waiting.
