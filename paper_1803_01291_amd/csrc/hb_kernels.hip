@@ -612,9 +612,15 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             long long kstep) {
     constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
     constexpr int SK_NOUTER = SK_QX * SK_QY - SK_RX * SK_RY;
+    // LDS row pitch of the R4 planes.  Regions wider than a wave (68 x 15)
+    // put the end of one row and the start of the next in one wave; a pitch
+    // of the region width plus 256 bytes keeps those two pieces in the bank
+    // order of one contiguous run (with the natural pitch 9% of the LDS
+    // cycles were bank conflicts; 2-3% of the step)
+    constexpr int SK_PX = SK_RX > 64 ? SK_RX + 256 / (int)sizeof(T) : SK_QX;
     static_assert(SK_NOUTER <= SK_RX * SK_RY, "one outer-ring column per thread at most");
-    __shared__ T pa[2][SK_QY][SK_QX];      // Y_phi at plane zi over R4 (double-buffered)
-    __shared__ T pb[2][SK_QY][SK_QX];      // S_phi,2 at plane zi over R4
+    __shared__ T pa[2][SK_QY][SK_PX];      // Y_phi at plane zi over R4 (double-buffered)
+    __shared__ T pb[2][SK_QY][SK_PX];      // S_phi,2 at plane zi over R4
     __shared__ T r3[3][SK_RY][SK_RX];      // S_phi,3 at planes zi-2..zi over R2
     __shared__ T r4[3][SK_RY][SK_RX];      // S_phi,4
 
@@ -776,8 +782,8 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
         T g1 = T(0), g2 = T(0);
         if (col_work && (per || (zi >= 0 && zi < nz))) {
             const int lx = rx + 2, ly = ry + 2;
-            const T(*A)[SK_QX] = pa[B];
-            const T(*Bp)[SK_QX] = pb[B];
+            const T(*A)[SK_PX] = pa[B];
+            const T(*Bp)[SK_PX] = pb[B];
             const T lapA = lap_z(K,
                                  lap_xy(K, yp0, A[ly][lx - 1] + A[ly][lx + 1], A[ly][lx - 2] + A[ly][lx + 2],
                                         A[ly - 1][lx] + A[ly + 1][lx], A[ly - 2][lx] + A[ly + 2][lx]),
