@@ -220,3 +220,37 @@ def test_serving_loop_reports_failed_requests(hb):
     by_index = {c.index: c for c in out["completions"]}
     assert out["failed"] == 1 and by_index[1].failed and not by_index[0].failed
     np.testing.assert_array_equal(by_index[0].phi, hb.solve_host(ws[0], 30)[0])
+
+
+def test_autotune_cache_file(hb, tmp_path, monkeypatch):
+    """HB_TUNE_CACHE: the first tuning appends one "key by zc" line; a later
+    solver of the same grid takes the cached choice without timing (here an
+    edited entry, to see it is read), and results do not depend on it."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HB_TUNE_CACHE", str(cache))
+    w = si.small_case(50, 30, 20, seed=41, steps=4)
+    p0, p1 = w.initial()
+
+    def tuned_run():
+        h = hb.hb_create(hb.config_from_workload(w))
+        try:
+            hb.hb_set_initial(h, p0, p1)
+            choice = hb.hb_autotune(h, 1)
+            hb.hb_step(h, 4)
+            phi = np.empty_like(p0)
+            hb.hb_read(h, phi, None)
+        finally:
+            hb.hb_destroy(h)
+        return choice, phi
+
+    first, phi1 = tuned_run()
+    lines = cache.read_text().split("\n")
+    lines = [l for l in lines if l]
+    assert len(lines) == 1
+    key, by, zc = lines[0].split()
+    assert (int(by), int(zc)) == first and "50x30x20" in key
+    cache.write_text(f"{key} 8 7\n")
+    second, phi2 = tuned_run()
+    assert second == (8, 7)
+    assert len([l for l in cache.read_text().split("\n") if l]) == 1  # a hit appends nothing
+    np.testing.assert_array_equal(phi1, phi2)
