@@ -612,12 +612,12 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
             long long kstep) {
     constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
     constexpr int SK_NOUTER = SK_QX * SK_QY - SK_RX * SK_RY;
-    // LDS row pitch of the R4 planes.  Regions wider than a wave (68 x 15)
-    // put the end of one row and the start of the next in one wave; a pitch
-    // of the region width plus 256 bytes keeps those two pieces in the bank
-    // order of one contiguous run (with the natural pitch 9% of the LDS
-    // cycles were bank conflicts; 2-3% of the step)
-    constexpr int SK_PX = SK_RX > 64 ? SK_RX + 256 / (int)sizeof(T) : SK_QX;
+    // LDS row pitch of the R4 planes.  Where a region row is not one wave
+    // (68 x 15, 36 x 28), one wave holds pieces of two or three rows; a pitch
+    // of the region width plus 256 bytes keeps those pieces in the bank order
+    // of one contiguous run (with the natural pitch 9% (68 x 15) and 16%
+    // (36 x 28) of the LDS cycles were bank conflicts; 2-7% of the step)
+    constexpr int SK_PX = SK_RX != 64 ? SK_RX + 256 / (int)sizeof(T) : SK_QX;
     static_assert(SK_NOUTER <= SK_RX * SK_RY, "one outer-ring column per thread at most");
     __shared__ T pa[2][SK_QY][SK_PX];      // Y_phi at plane zi over R4 (double-buffered)
     __shared__ T pb[2][SK_QY][SK_PX];      // S_phi,2 at plane zi over R4

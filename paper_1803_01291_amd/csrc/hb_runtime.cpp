@@ -561,14 +561,21 @@ int default_zc_step(const Layout& L, int by, int nmembers) {
 }
 
 // Default region shape of a single solve: 64 x 16, or 68 x 15 where the march
-// model gives it at least 5% fewer block-planes.  68 x 15 regions cost a few
-// percent more per block (rows are not waves) but their 64-column tiles cover
-// multiples of 64 without a ragged tile and start on 128-byte lines; measured
-// (FP64 / FP32c): 256^3 -3.5% / -1.5%, 512^3 -3% / -8%, 512 x 512 x 64 -6% /
-// -7% (model 13-22% fewer), 500^3, 384^3, 192^3 +2 to +4% (model 0-5% fewer,
-// so 64 x 16 stays).  Batches and pools keep 64 x 16.
-int default_step_by(const Layout& L) {
-    return plan_zc_step(L, 11).cost <= 0.95 * plan_zc_step(L, 16).cost ? 11 : 16;
+// model gives it at least 3% (FP64) / 5% (FP32c) fewer block-planes, or
+// 36 x 28 where the model gives that at least 8% (FP64) / 15% (FP32c) fewer
+// block-planes than the better of the other two.  The model overstates the differences (a block's
+// cost also depends on its shape), so the margins are set from measurements
+// on eight grids (192^3 to 512^3, a 512 x 512 x 64 slab; both precisions;
+// two devices): the rule picks the fastest shape or one within 2% of it in
+// 31 of the 32 cases (192^3 FP32c: 4%), e.g. 68 x 15 on 256^3 and 512^3,
+// 36 x 28 on 384^3 (FP64 -8% against 64 x 16).  Batches and pools keep
+// 64 x 16.
+int default_step_by(const Layout& L, int precision) {
+    const double c16 = plan_zc_step(L, 16).cost, c11 = plan_zc_step(L, 11).cost;
+    const double c8 = plan_zc_step(L, 8).cost;
+    const bool f32c = precision == HB_F32C;
+    if (c8 <= (f32c ? 0.85 : 0.92) * std::min(c16, c11)) return 8;
+    return c11 <= (f32c ? 0.95 : 0.97) * c16 ? 11 : 16;
 }
 
 void make_tiles(const Solve& s, int solve_index, int scheme, int by, int zc_req, int nmembers,
@@ -796,7 +803,7 @@ int hb_create(const hb_config* cfg, hb_solver** out) {
     HB_TRY(ensure_ctab(*h->s, 4096, h->stream, nullptr));
     h->g.prec = cfg->precision;
     h->g.scheme = scheme_of(cfg->flags);
-    h->g.by = h->g.scheme == SCHEME_STEP ? default_step_by(h->s->L) : DEFAULT_BY;
+    h->g.by = h->g.scheme == SCHEME_STEP ? default_step_by(h->s->L, cfg->precision) : DEFAULT_BY;
     h->g.members.push_back(h->s.get());
     HIP_TRY(hipStreamSynchronize(h->stream));
     *out = h.release();
