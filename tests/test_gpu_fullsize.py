@@ -94,7 +94,7 @@ def test_cube256_10_steps_every_node(hb, oracle_mod):
 
 def test_slab512x512x64_10_steps_every_node(hb, oracle_mod):
     """The benchmark's shard leg (one GPU's z-slab of the 512^3 workload, its
-    own tiling: 64-plane marches over 387 tiles), every node."""
+    own default tiling: 64 x 11 tiles, 32-plane marches), every node."""
     w = si.slab_config()
     for prec, tol in ((0, 1e-12), (1, 1e-5)):
         phi, psi, _ = gpu_run(hb, w, 10, precision=prec)
