@@ -11,6 +11,8 @@ imports nothing from them.
 * ``laplacian``  -- the 13-point operator on a caller-filled padded array.
 * ``radial``     -- the radial 1-D form of section 2.2 (NumPy).
 * ``diagnostics``-- plain FP64 definitions of the observables.
+* ``components`` -- bubble count: connected sets of each sign (section 1),
+                    breadth-first flood fill in plain C.
 """
 from __future__ import annotations
 
@@ -68,6 +70,8 @@ def _load() -> ctypes.CDLL:
     lib.hbo_set_threads.restype = None
     lib.hbo_get_threads.argtypes = []
     lib.hbo_get_threads.restype = i
+    lib.hbo_components.argtypes = [i, i, i, i, dp, d, ctypes.POINTER(ll), ctypes.POINTER(ll)]
+    lib.hbo_components.restype = i
     _lib = lib
     return lib
 
@@ -127,6 +131,22 @@ def solve(phi0: np.ndarray, psi0: np.ndarray, h: Sequence[float], mu2: float, la
     if rc != 0:
         raise RuntimeError(f"hbo_solve failed: {rc}")
     return phi, psi
+
+
+def components(phi: np.ndarray, eps: float = 0.0, bc: int = BC_ZERO) -> Tuple[int, int]:
+    """Number of maximal face-connected node sets of {phi < -eps} and of
+    {phi > eps} (the paper's bubbles, section 1; ``bc`` = BC_PERIODIC wraps
+    neighbours).  Returns (negative sets, positive sets)."""
+    phi = np.ascontiguousarray(phi, np.float64)
+    if phi.ndim != 3:
+        raise ValueError("phi must be a 3-D [nz][ny][nx] array")
+    nz, ny, nx = phi.shape
+    nneg, npos = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    rc = _load().hbo_components(nx, ny, nz, bc, _ptr(phi), float(eps), ctypes.byref(nneg),
+                                ctypes.byref(npos))
+    if rc != 0:
+        raise RuntimeError(f"hbo_components failed: {rc}")
+    return int(nneg.value), int(npos.value)
 
 
 def solve_workload(w, nsteps: Optional[int] = None, order: int = ORDER_TEXTBOOK):

@@ -11,6 +11,9 @@
 * nonfinite  number of NaN/Inf entries in phi and psi
 * negative   number of interior points with phi < 0 (sign-change probe for
              the paper's bubbles, section 1)
+* bubbles    the paper's bubbles (section 1: maximal connected sets where the
+             solution changes sign): the number of face-connected node sets
+             of {phi < -eps} and of {phi > eps} (``components`` in the C part)
 """
 from __future__ import annotations
 
@@ -18,7 +21,7 @@ import math
 
 import numpy as np
 
-from . import laplacian
+from . import BC_PERIODIC, BC_ZERO, components, laplacian
 
 
 def _lap_zero_halo(phi: np.ndarray, h) -> np.ndarray:
@@ -45,3 +48,9 @@ def diagnostics(phi: np.ndarray, psi: np.ndarray, h, mu2: float, lam: float, t: 
         "nonfinite": int(np.count_nonzero(~np.isfinite(phi)) + np.count_nonzero(~np.isfinite(psi))),
         "negative": int(np.count_nonzero(phi < 0)),
     }
+
+
+def bubbles(phi: np.ndarray, eps: float = 0.0, periodic: bool = False) -> tuple:
+    """(negative sets, positive sets): face-connected components of
+    {phi < -eps} and {phi > eps} over the interior nodes."""
+    return components(phi, eps, BC_PERIODIC if periodic else BC_ZERO)

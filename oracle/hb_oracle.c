@@ -302,3 +302,73 @@ int hbo_get_threads(void) {
     return 1;
 #endif
 }
+
+/*
+ * Bubble count (section 1: a bubble is a maximal connected set of points at
+ * which the solution changes sign).  On the grid, the sign classes are the
+ * node sets {phi < -eps} and {phi > eps} (eps >= 0; eps = 0 is the sign
+ * itself, a positive eps ignores values of magnitude <= eps), and two nodes
+ * are connected when they are face neighbours (6-connectivity); with
+ * periodic boundaries the neighbour index wraps, otherwise the grid ends at
+ * the boundary.  *nneg and *npos receive the number of maximal connected
+ * sets of each class.  Plain breadth-first flood fill from every unvisited
+ * node in index order, with an explicit queue.  NaN belongs to neither class.
+ */
+static int sign_class(double v, double eps) {
+    if (v < -eps) return 1;
+    if (v > eps) return 2;
+    return 0;
+}
+
+int hbo_components(int nx, int ny, int nz, int bc, const double* phi, double eps,
+                   long long* nneg, long long* npos) {
+    if (nx < 1 || ny < 1 || nz < 1 || !phi || !nneg || !npos || !(eps >= 0.0)) return HBO_E_ARG;
+    const grid_t g = {nx, ny, nz, nx + 4, ny + 4, nz + 4};
+    const size_t n = (size_t)nx * (size_t)ny * (size_t)nz;
+    unsigned char* seen = (unsigned char*)calloc(n, 1);
+    size_t* queue = (size_t*)malloc(n * sizeof(size_t));
+    if (!seen || !queue) {
+        free(seen);
+        free(queue);
+        return HBO_E_NOMEM;
+    }
+    long long count[3] = {0, 0, 0};
+    for (size_t start = 0; start < n; ++start) {
+        const int cls = sign_class(phi[start], eps);
+        if (cls == 0 || seen[start]) continue;
+        count[cls] += 1;
+        size_t head = 0, tail = 0;
+        queue[tail++] = start;
+        seen[start] = 1;
+        while (head < tail) {
+            const size_t at = queue[head++];
+            const int i = (int)(at % (size_t)nx);
+            const int j = (int)((at / (size_t)nx) % (size_t)ny);
+            const int k = (int)(at / ((size_t)nx * (size_t)ny));
+            for (int d = 0; d < 6; ++d) {
+                int a = i, b = j, c = k;
+                const int step = (d & 1) ? 1 : -1;
+                if (d < 2) a += step;
+                else if (d < 4) b += step;
+                else c += step;
+                if (bc == HBO_BC_PERIODIC) {
+                    a = wrap(a, nx);
+                    b = wrap(b, ny);
+                    c = wrap(c, nz);
+                } else if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz) {
+                    continue;
+                }
+                const size_t nb = iidx(&g, a, b, c);
+                if (!seen[nb] && sign_class(phi[nb], eps) == cls) {
+                    seen[nb] = 1;
+                    queue[tail++] = nb;
+                }
+            }
+        }
+    }
+    free(seen);
+    free(queue);
+    *nneg = count[1];
+    *npos = count[2];
+    return HBO_OK;
+}
