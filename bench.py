@@ -7,16 +7,20 @@ whole-step kernel + the step-counter tick) over the whole grid; inputs are
 resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra objects:
-  roofline      -- the whole-step kernel (one launch per RK4 step): the
-                   contract's algorithmic bytes per point-step (152 B FP64,
-                   the 19 field passes of one-pass-per-stage RK4) x points /
-                   the kernel's mean duration from HIP events on the solver's
-                   stream, against 8 TB/s.  The kernel itself moves only
-                   32 B/point (Y in, Y' out): own_GBps/own_frac price that,
-                   own_frac_of_copy against the measured copy ceiling;
-                   traffic is the PMC-measured bytes per launch;
+  roofline      -- the whole-step kernel (one launch per RK4 step): its
+                   algorithmic bytes, 32 B per interior point (the state slot
+                   of every point read once and written once: the floor for
+                   a method that reads and writes the state once per step) x
+                   points / the kernel's mean duration from HIP events on the
+                   solver's stream, against 8 TB/s (frac must stay <= 1).
+                   The one-pass-per-stage figure of 152 B/point (19 field
+                   passes) is kept as contract_19pass_equiv_GBps: the rate a
+                   stage-by-stage design would need to match this kernel;
+                   traffic is the PMC-measured bytes per launch and
+                   traffic_over_alg its ratio to the 32 B/point;
   cpu_baseline  -- the FP64 CPU oracle on a bounded number of steps of the
-                   same grid, on this host's cores;
+                   same grid, on all of this host's cores (OpenMP), with a
+                   one-thread run of fewer steps beside it (single_thread);
   forms         -- the same step rate for the FP32c form (same grid);
   hbm_probe     -- the streamed-bandwidth ceiling measured by the library's
                    copy and 5-read/2-write probe kernels;
@@ -35,6 +39,10 @@ Prints ONE JSON line.  Extra objects:
                    default grid, 500^3 cells, dt = 1e-4, FP64 and FP32c: step
                    rate and the projected hours to t = 50 (5e5 steps) beside
                    the paper's 27 h;
+  precision_c3  -- the precision form's own workload (512^3 C-infinity bump,
+                   1000 steps): FP64 and FP32c run times, FP32c against FP64
+                   over the grid (max and L2) and both against the oracle's
+                   stored sample nodes;
   accuracy      -- after the workload's 2000 steps, FP64 and FP32c: relative
                    max error at the oracle's stored sample nodes, and FP32c
                    against FP64 over the whole grid (max and L2);
@@ -43,6 +51,7 @@ Prints ONE JSON line.  Extra objects:
 """
 import argparse
 import json
+import math
 
 import numpy as np
 import os
@@ -189,7 +198,65 @@ def run_shard(steps, warmup):
     return {"grid": [512, 512, 64], "steps": steps,
             "pt_updates_per_s": sw.points * steps / elapsed,
             "ms_per_step": elapsed / steps * 1e3, "kernel_ms": sum(stage_ms),
-            "own_GBps": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9}
+            "GBps": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9,
+            "frac": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def run_precision_c3(steps):
+    """The precision form on its own workload: 512^3 on [-32,32]^3, the
+    C-infinity bump (A = 0.8, R = 10), mu^2 = 2, lambda = 1, dt = 0.005,
+    `steps` steps from the initial data, FP64 and FP32c on the GPU.  Reports
+    each run's time and, after the last step, the FP32c error against FP64
+    over the whole grid (state-vector relative max norm and relative L2) and
+    both against the oracle's values at the nodes stored by
+    tests/golden/make_golden.py (when the stored run has this many steps)."""
+    import torch
+    import synth_inputs as si
+    from paper_1803_01291_amd import hb
+    w = si.config3(steps=steps)
+    p0, p1 = w.initial()
+    dev = torch.device("cuda")
+    out = {"grid": list(w.n), "steps": steps, "dt": w.dt}
+    st = {}
+    for prec, name in ((0, "f64"), (1, "f32c")):
+        h = hb.hb_create(hb.config_from_workload(w, prec))
+        try:
+            hb.hb_set_initial(h, p0, p1)
+            hb.hb_sync(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hb.hb_step(h, steps)
+            hb.hb_sync(h)
+            el = time.perf_counter() - t0
+            phi = torch.empty(tuple(w.n[::-1]), dtype=torch.float64, device=dev)
+            psi = torch.empty_like(phi)
+            hb.hb_read(h, phi, psi)
+        finally:
+            hb.hb_destroy(h)
+        st[name] = (phi, psi)
+        out[name] = {"seconds": el, "ms_per_step": el / steps * 1e3,
+                     "pt_updates_per_s": w.points * steps / el}
+    out["f32c_speedup_vs_f64"] = out["f64"]["seconds"] / out["f32c"]["seconds"]
+    (a, b), (c, d) = st["f64"], st["f32c"]
+    den = max(a.abs().max().item(), b.abs().max().item())
+    out["f32c_vs_f64_rel_max"] = max((c - a).abs().max().item(), (d - b).abs().max().item()) / den
+    out["f32c_vs_f64_rel_l2"] = (math.sqrt(((c - a) ** 2).sum().item() + ((d - b) ** 2).sum().item())
+                                 / math.sqrt((a ** 2).sum().item() + (b ** 2).sum().item()))
+    path = os.path.join(ROOT, "tests", "golden", "cube512_cinfbump_oracle.json")
+    if os.path.exists(path):
+        g = json.load(open(path))
+        if g["steps"] == steps and list(w.n) == g["n"]:
+            pts = torch.tensor(g["points_zyx"], device=dev)
+            gp = torch.tensor(g["phi"], dtype=torch.float64, device=dev)
+            gs = torch.tensor(g["psi"], dtype=torch.float64, device=dev)
+            gden = max(g["max_abs_phi"], g["max_abs_psi"])
+            for name, (p, q) in st.items():
+                vp = p[pts[:, 0], pts[:, 1], pts[:, 2]]
+                vq = q[pts[:, 0], pts[:, 1], pts[:, 2]]
+                out[name]["vs_oracle_sampled_rel_max"] = max((vp - gp).abs().max().item(),
+                                                             (vq - gs).abs().max().item()) / gden
+            out["oracle_nodes"] = len(g["points_zyx"])
+    return out
 
 
 def run_paper_grid(steps, warmup):
@@ -322,16 +389,32 @@ def run_accuracy(w):
             "f32c_vs_f64_rel_l2": float(l2 / l2ref)}
 
 
-def cpu_baseline(w, steps):
+def cpu_baseline(w, steps, steps_1t):
+    """The FP64 C oracle on `steps` RK4 steps of the workload's grid on all
+    host threads (OpenMP over z-planes), and on `steps_1t` steps with one
+    thread; its results do not depend on the thread count."""
     import oracle
     p0, p1 = w.initial()
+    nthr = oracle.get_threads()
     t0 = time.perf_counter()
     oracle.solve(p0, p1, w.h, w.mu2, w.lam, w.dt, steps, t0=w.t0, inv_L2=w.inv_L2)
     dt = time.perf_counter() - t0
-    return {"value": w.points * steps / dt, "unit": "grid-point-updates/s",
-            "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the same {w.n[0]}^3 grid (FP64 C oracle, OpenMP), "
-                      f"{dt:.1f} s"}
+    out = {"value": w.points * steps / dt, "unit": "grid-point-updates/s",
+           "cores": nthr, "kind": "oracle",
+           "sample": f"{steps} RK4 steps of the same {w.n[0]}^3 grid (FP64 C oracle, OpenMP, "
+                     f"{nthr} threads), {dt:.1f} s"}
+    if steps_1t > 0:
+        oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle.solve(p0, p1, w.h, w.mu2, w.lam, w.dt, steps_1t, t0=w.t0, inv_L2=w.inv_L2)
+            d1 = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(nthr)
+        out["single_thread"] = {"value": w.points * steps_1t / d1, "cores": 1,
+                                "sample": f"{steps_1t} RK4 steps of the same grid, one thread, "
+                                          f"{d1:.1f} s"}
+    return out
 
 
 def main():
@@ -342,6 +425,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--stage-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps-1t", type=int, default=20,
+                    help="steps of the one-thread oracle run (0 skips it)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=500)
@@ -357,6 +442,9 @@ def main():
     ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the error check of the workload against the stored oracle samples")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the precision form's own workload (512^3, 1000 steps, FP64 vs FP32c)")
+    ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--no-paper-grid", action="store_true",
                     help="skip the paper's default-grid leg (Example 7, 500^3, dt 1e-4)")
     ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
@@ -385,12 +473,19 @@ def main():
     # kernels are summed over the step
     kernel_ms = sum(stage_ms)
     rate = N * args.steps / elapsed
-    # algorithmic bytes per launch: the per-point-step figure of the
-    # measurement contract (152 B FP64 = 19 field passes) x interior points
-    achieved = sum(STAGEWISE_BYTES[0]) * N / (kernel_ms * 1e-3) / 1e9
+    # algorithmic bytes per launch of the timed scheme: the whole-step kernel
+    # reads and writes each point's 16-byte state slot once (32 B/point), the
+    # stage-pair kernels move 80 B, the per-stage kernels 152 B
     own_b = {"step": STEP_BYTES[0], "pairs": 80, "stages": sum(STAGEWISE_BYTES[0])}[args.scheme]
-    own = own_b * N / (kernel_ms * 1e-3) / 1e9
-    step_alg = sum(STAGEWISE_BYTES[0]) * N
+    achieved = own_b * N / (kernel_ms * 1e-3) / 1e9
+    frac = achieved / HBM_PEAK_GBS
+    if not frac <= 1.0:
+        raise SystemExit(f"roofline fraction {frac:.3f} > 1: the kernel time or the byte count is wrong")
+    # the one-pass-per-stage contract (152 B FP64 = 19 field passes) priced on
+    # the same kernel time: the rate a stage-by-stage design would need
+    contract = sum(STAGEWISE_BYTES[0]) * N / (kernel_ms * 1e-3) / 1e9
+    traffic = (TRAFFIC_BYTES_F64 if source_sha() == TRAFFIC_SOURCE_SHA and args.n == 256
+               and args.scheme == "step" else None)
     out = {
         "metric": "RK4 grid-point updates/s + % HBM roofline; batched solves/s, p50/p99 latency",
         "value": rate,
@@ -408,19 +503,16 @@ def main():
                                f"8 seeded Gaussians, dt=0.005, FP64",
                    "grid": [args.n] * 3, "dt": w.dt, "precision": "f64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (TRAFFIC_BYTES_F64
-                                 if source_sha() == TRAFFIC_SOURCE_SHA and args.n == 256
-                                 and args.scheme == "step" else None),
+                     "frac": frac, "traffic": traffic,
+                     "traffic_over_alg": traffic / (own_b * N) if traffic else None,
                      "kernel": {"step": "step_kernel (whole RK4 step)",
                                 "pairs": "pair_kernel x 2 (sum per step)",
                                 "stages": "stage_kernel x 4 (sum per step)"}[args.scheme],
                      "kernel_ms": kernel_ms,
-                     "bytes_per_point": sum(STAGEWISE_BYTES[0]),
-                     "own_bytes_per_point": own_b,
-                     "own_GBps": own, "own_frac": own / HBM_PEAK_GBS,
-                     "step_alg_GBps": step_alg / (elapsed / args.steps) / 1e9,
-                     "step_frac": step_alg / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
+                     "bytes_per_point": own_b,
+                     "contract_19pass_bytes_per_point": sum(STAGEWISE_BYTES[0]),
+                     "contract_19pass_equiv_GBps": contract,
+                     "step_frac": own_b * N / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
         # the paper's only timing (section 2.1): 27 h to reach t = 50 on one
         # Tesla K40c, with the default grid and step of section 3 (500^3
@@ -436,8 +528,10 @@ def main():
         k32 = sum(ms32)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
                                  "kernel_ms": k32,
-                                 "alg_GBps": sum(STAGEWISE_BYTES[1]) * N / (k32 * 1e-3) / 1e9,
-                                 "own_GBps": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9}}
+                                 "GBps": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9,
+                                 "frac": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "contract_19pass_equiv_GBps":
+                                     sum(STAGEWISE_BYTES[1]) * N / (k32 * 1e-3) / 1e9}}
     if not args.no_probe:
         from paper_1803_01291_amd import hb
         gib = 1 << 30
@@ -446,7 +540,7 @@ def main():
                             "read5_write2_GBps": hb.hb_probe_bandwidth(2, gib // 2, 20),
                             "bytes_per_array": [gib, gib // 2]}
         # the kernel's own bytes against the measured streaming ceiling
-        out["roofline"]["own_frac_of_copy"] = out["roofline"]["own_GBps"] / copy
+        out["roofline"]["frac_of_copy"] = achieved / copy
     if not args.no_batch:
         out["batched"] = run_batch(args.batch_count, args.batch_steps, 16)
     if not args.no_serve:
@@ -464,13 +558,15 @@ def main():
         out["accuracy"] = run_accuracy(w)
     if not args.no_shard:
         out["shard"] = run_shard(200, 10)
+    if not args.no_c3:
+        out["precision_c3"] = run_precision_c3(args.c3_steps)
     if not args.no_paper_grid:
         out["paper_grid"] = run_paper_grid(200, 10)
     if not args.no_radial:
         out["radial"] = run_radial(args.radial_count, 1000, args.radial_steps,
                                    0 if args.no_cpu else 4)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)
 
 
