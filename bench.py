@@ -26,7 +26,8 @@ Prints ONE JSON line.  Extra objects:
                    copy and 5-read/2-write probe kernels;
   batched       -- 64 uneven solves (N ~ U{64..192}^3, 500 steps), one
                    whole-step launch per step and precision over all of them,
-                   FP64 and FP32c, vs the same solves run one by one;
+                   FP64 and FP32c, tiles from the batch autotuner (default
+                   tiles timed beside), vs the same solves run one by one;
   served        -- a Poisson request stream (50/s, N in {48..384}^3, 200-2000
                    steps, FP64/FP32c) through the continuous-batching pool:
                    p50/p99 latency and solves/s (offered load is far above
@@ -117,11 +118,13 @@ def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0):
     return elapsed, [m / timed_stage_steps for m in stage_ms], d
 
 
-def run_batch(count, steps, warmup):
+def run_batch(count, steps, warmup, tune_steps=3):
     """64 uneven solves (N ~ U{64..192}^3) advanced together: one whole-step
     launch per step and precision over a tile table spanning all solves, hipGraph
-    replay of 16-step chunks.  Baseline: the same solves one after another
-    through the single-solve path (also graph-replayed), same GPU."""
+    replay of 16-step chunks, tiles chosen by the library's autotuner
+    (hb_batch_autotune; the default tiles are timed first, for comparison).
+    Baseline: the same solves one after another through the single-solve path
+    (also graph-replayed), same GPU."""
     import torch
     import synth_inputs as si
     from paper_1803_01291_amd import hb
@@ -136,6 +139,15 @@ def run_batch(count, steps, warmup):
         try:
             for i in range(count):
                 hb.hb_batch_set_initial(b, i, data[i], None)
+            hb.hb_batch_step(b, warmup)
+            hb.hb_batch_sync(b)
+            t0 = time.perf_counter()
+            hb.hb_batch_step(b, steps)
+            hb.hb_batch_sync(b)
+            tdef = time.perf_counter() - t0
+            # the library's autotuner picks this group's tiles (states are
+            # restored), then the same number of steps is timed again
+            choice = hb.hb_batch_autotune(b, tune_steps)[prec]
             hb.hb_batch_step(b, warmup)
             hb.hb_batch_sync(b)
             t0 = time.perf_counter()
@@ -162,6 +174,8 @@ def run_batch(count, steps, warmup):
             for h in handles:
                 hb.hb_destroy(h)
         out[name] = {"seconds": tb, "solves_per_s": count / tb, "pt_updates_per_s": pts * steps / tb,
+                     "tiles": {"by": choice[0], "zc": choice[1], "chosen_by": "hb_batch_autotune"},
+                     "default_tiles_seconds": tdef, "tuned_speedup_vs_default": tdef / tb,
                      "sequential_seconds": ts, "speedup_vs_sequential": ts / tb}
     out["f32c_speedup_vs_f64"] = out["f64"]["seconds"] / out["f32c"]["seconds"]
     return out

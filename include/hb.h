@@ -134,12 +134,18 @@ int hb_create(const hb_config* cfg, hb_solver** out);
  * returns; device inputs are read in stream order. */
 int hb_set_initial(hb_solver* s, const void* phi0, const void* phi1, int mem, int dtype);
 
-/* Restore a checkpoint: state (phi, psi) at step n (t = t0 + n dt), 0 <= n
- * <= 2^40; psi may be NULL for zero.  Stepping on from it is bitwise the same
- * as never having stopped. */
+/* Restore a checkpoint: the state vector v = (phi, phi_t) of eq. (rhs)
+ * (section 2.1) at step n, 0 <= n <= 2^40; psi (= phi_t) may be NULL for
+ * zero.  The time is not an argument: it is t = t0 + n dt, computed by
+ * multiplication as for every step, so a resumed solve sees the stage times
+ * it would have seen without stopping and stepping on is bitwise the same as
+ * never having stopped.  Arrays as for hb_set_initial. */
 int hb_set_state(hb_solver* s, const void* phi, const void* psi, int64_t n, int mem, int dtype);
 
-/* Enqueue nsteps RK4 steps on the solver's stream and return without waiting.
+/* Enqueue nsteps steps of the classical fourth-order Runge-Kutta method of
+ * section 2.1 (stages at t_n, t_n + dt/2, t_n + dt/2, t_n + dt, t_n = t0 +
+ * n dt) applied to eq. (rhs), on the solver's stream, and return without
+ * waiting.
  * Each step is one whole-step kernel (default), 2 stage-pair kernels
  * (HB_PAIRWISE) or 4 per-stage kernels (HB_STAGEWISE); a tiny kernel advances
  * the device step counter after each batch of steps.  HB_E_STATE before
@@ -155,8 +161,11 @@ int hb_step(hb_solver* s, int64_t nsteps);
  * unused entries are 0.  For measurement. */
 int hb_step_timed(hb_solver* s, int64_t nsteps, double* stage_ms);
 
-/* Wait for the solver's stream, then copy the interior state out.  Either
- * output may be NULL.  For HB_F32C the value returned is hi + lo in FP64. */
+/* Wait for the solver's stream, then copy the interior state vector
+ * v = (phi, phi_t) of eq. (rhs) (section 2.1) out: phi into `phi`, phi_t
+ * into `phi_t`, each nz*ny*nx values of `dtype` in `mem` (C order, x
+ * fastest).  Either output may be NULL.  For HB_F32C the value returned is
+ * hi + lo in FP64 (rounded to FP32 for HB_DTYPE_F32). */
 int hb_read(hb_solver* s, void* phi, void* phi_t, int mem, int dtype);
 
 /* Current time and step count (host bookkeeping; no wait). */
@@ -168,6 +177,16 @@ int hb_sync(hb_solver* s);
 /* FP64 diagnostics (deterministic fixed-order reductions); waits.  Returns
  * HB_E_NONFINITE (with *out filled) when the state holds NaN/Inf. */
 int hb_diagnostics(hb_solver* s, hb_diag* out);
+
+/* The paper's bubbles (section 1: maximal connected sets on which the
+ * solution has changed sign) in the current state: *negative_sets = the
+ * number of maximal face-connected (6-neighbour) sets of interior points
+ * with phi < -eps, *positive_sets likewise for phi > eps (periodic solves:
+ * neighbours wrap across the faces).  eps >= 0 (0: the sign itself).  FP32c
+ * states are classed on hi + lo in FP64.  Keeps a label array of 4 bytes per
+ * interior point from the first call (grids of at most 2^32 - 2 points,
+ * HB_E_ARG beyond).  Waits.  HB_E_STATE before initial data. */
+int hb_bubbles(hb_solver* s, double eps, int64_t* negative_sets, int64_t* positive_sets);
 
 /* Tile shape: zc >= 1 planes per tile (0 = library default: for the
  * whole-step kernel, the length that best fills whole rounds of resident
@@ -228,6 +247,15 @@ int hb_batch_step(hb_batch* b, int64_t nsteps);
 int hb_batch_read(hb_batch* b, int i, void* phi, void* phi_t, int mem, int dtype);
 int hb_batch_sync(hb_batch* b);
 int hb_batch_set_tiling(hb_batch* b, int by, int zc);
+/* The library's autotuner over a batch: for each precision group (index 0
+ * FP64, 1 FP32c) every candidate tile shape and z-march length is timed for
+ * trial_steps steps from the current states, the fastest is kept for that
+ * group, and every state is restored bitwise.  by[2] and zc[2] (either may
+ * be NULL) receive the choices, -1 for an empty group.  With HB_TUNE_CACHE
+ * set, choices are cached per device, precision, scheme and mix of member
+ * grids (a batch with the same grid sizes hits the entry).  Results do not
+ * depend on the tiling.  HB_E_STATE before every solve has initial data. */
+int hb_batch_autotune(hb_batch* b, int trial_steps, int* by, int* zc);
 int hb_batch_destroy(hb_batch* b);
 
 /* ---- served form: continuous batching of admitted solves ------------------ */

@@ -14,9 +14,12 @@ Discretisation (section 2.2 and the section 2.1 stencil):
   section 2.2), and zeros beyond r = R;
 * r = 0: L'Hospital, phi_r / r -> phi_rr(0), so the radial operator there is
   3 phi_rr(0) with phi_rr(0) = (-5/2 u0 + 8/3 u1 - 1/6 u2) / dr^2 (section 2.2);
-* time: classical RK4 as in section 2.1.
+* time: classical RK4 as in section 2.1; c(t) at each stage time is the C
+  library's FP64 exp (``math.exp``), the values the 3-D oracle uses.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -48,7 +51,7 @@ def radial_operator(u: np.ndarray, dr: float) -> np.ndarray:
 
 def radial_rhs(t: float, phi: np.ndarray, psi: np.ndarray, dr: float, mu2: float, lam: float,
                inv_L2: float):
-    c = np.exp(-2.0 * t) * inv_L2
+    c = math.exp(-2.0 * t) * inv_L2
     return psi, -3.0 * psi + c * radial_operator(phi, dr) + mu2 * phi - lam * phi * phi * phi
 
 

@@ -99,6 +99,13 @@ int diag_partials_needed(int nx, int ny, int nz);
 int launch_diagnostics(int prec, const SolveDesc* desc, int parity, double c, double* partials,
                        int nparts, double* out, void* stream);
 
+// Bubbles (section 1): the number of face-connected node sets of {phi < -eps}
+// (counts[0]) and of {phi > eps} (counts[1]) over the interior (periodic
+// solves wrap).  labels: `points` (< 2^32 - 1) entries of scratch; counts:
+// two entries, written by the launch.
+int launch_bubbles(int prec, const SolveDesc* desc, int parity, double eps, long long points,
+                   unsigned* labels, unsigned long long* counts, void* stream);
+
 // Bandwidth probe: kind 0 = copy (1 read, 1 write), 1 = add (2 reads, 1 write),
 // 2 = 5 reads + 2 writes (the FP64 stage-4 stream mix).  n16 elements of 16 B.
 int launch_probe(int kind, void* const* in, void* const* out, long long n16, int blocks,
@@ -109,14 +116,16 @@ int launch_probe(int kind, void* const* in, void* const* out, long long n16, int
 struct RadialDesc {
     long long offset;  // first node of this solve in phi/psi
     long long steps;
+    long long ctab;    // first entry of this solve's c(t) rows in the launch's table:
+                       // ctab[ctab + 3 (n - n0) + {0, 1, 2}] = c at t_n, t_n + dt/2, t_n + dt
     int m;             // nodes r_i = i dr, i = 0..m-1 (phi = 0 at r = m dr)
     int pad_;
     double dr, mu2, lambda, inv_L2, t0, dt;
 };
 size_t radial_lds_bytes(int max_m);
 // steps n0 <= n < min(n1, steps) of every solve (state read from and
-// written back to phi, psi)
-int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
-                  long long n0, long long n1, void* stream);
+// written back to phi, psi); ctab holds each solve's c(t) rows for those steps
+int launch_radial(const RadialDesc* descs, const double* ctab, int count, int max_m, double* phi,
+                  double* psi, long long n0, long long n1, void* stream);
 
 }  // namespace hb

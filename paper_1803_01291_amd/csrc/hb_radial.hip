@@ -16,9 +16,17 @@
 // stage needs one barrier.  The owners of nodes 1 and 2 also write the even
 // ghosts S[-1], S[-2].  Stage inputs are formed as in the 3-D kernels (G
 // storage: only the psi component of each stage derivative is kept).
+// c(t) comes from a host FP64 table (c at t_n, t_n + dt/2 and t_n + dt for
+// each step of the launch), the values the 3-D path and the oracles use, and
+// the per-node arithmetic follows the plain definition's operation order
+// (difference quotients divided by dr^2 and 12 dr, no contraction).
 #include <hip/hip_runtime.h>
 
 #include "hb_internal.h"
+
+// every expression of this file is evaluated as written (no fused
+// multiply-adds), in the plain definition's order
+#pragma clang fp contract(off)
 
 namespace hb {
 namespace {
@@ -30,8 +38,8 @@ using gptr = __attribute__((address_space(1))) T*;
 
 template <int NPT>
 __global__ void __launch_bounds__(RAD_THREADS)
-radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
-              double* __restrict__ psi, long long n0, long long n1) {
+radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ ctab,
+              double* __restrict__ phi, double* __restrict__ psi, long long n0, long long n1) {
     extern __shared__ double lds[];
     const RadialDesc d = descs[blockIdx.x];
     const int m = d.m;
@@ -55,7 +63,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
 
     const double dr = d.dr, mu2 = d.mu2, lam = d.lambda, dt = d.dt;
     const double hdt = dt / 2.0, dt6 = dt / 6.0;
-    const double idr2 = 1.0 / (dr * dr), i12dr = 1.0 / (12.0 * dr);
+    const double dr2 = dr * dr, dr12 = 12.0 * dr;
 
     // 2/r at the owned nodes, divided once (kept in registers up to 8 nodes
     // per thread; recomputed, with the same result, beyond)
@@ -70,9 +78,9 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
     auto op = [&](const double* S, int i, int k) {
         const double um2 = S[i - 2], um1 = S[i - 1], u0 = S[i], up1 = S[i + 1], up2 = S[i + 2];
         const double urr = (-1.0 / 12.0 * um2 + 4.0 / 3.0 * um1 - 5.0 / 2.0 * u0 + 4.0 / 3.0 * up1
-                            - 1.0 / 12.0 * up2) * idr2;
+                            - 1.0 / 12.0 * up2) / dr2;
         if (i == 0) return 3.0 * urr;
-        const double ur = (um2 - 8.0 * um1 + 8.0 * up1 - up2) * i12dr;
+        const double ur = (um2 - 8.0 * um1 + 8.0 * up1 - up2) / dr12;
         const double tr = KEEP_2R ? two_r[KEEP_2R ? k : 0] : 2.0 / ((double)i * dr);
         return tr * ur + urr;
     };
@@ -89,11 +97,11 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
     };
 
     const long long nend = d.steps < n1 ? d.steps : n1;
+    const gptr<const double> ct = (gptr<const double>)(ctab + d.ctab);
     for (long long n = n0; n < nend; ++n) {
-        const double t = d.t0 + (double)n * dt;
-        const double c1 = exp(-2.0 * t) * d.inv_L2;
-        const double c2 = exp(-2.0 * (t + dt / 2.0)) * d.inv_L2;
-        const double c4 = exp(-2.0 * (t + dt)) * d.inv_L2;
+        // c(t) at the stage times of step n (host FP64 table of this launch)
+        const long long j = 3 * (n - n0);
+        const double c1 = ct[j], c2 = ct[j + 1], c4 = ct[j + 2];
         // stage 1: S = Y_phi, S_psi = Y_psi
 #pragma unroll
         for (int k = 0; k < NPT; ++k) sv[k] = yp[k];
@@ -165,15 +173,15 @@ radial_kernel(const RadialDesc* __restrict__ descs, double* __restrict__ phi,
 }
 
 template <int NPT>
-hipError_t launch_radial_t(const RadialDesc* descs, int count, size_t bytes, double* phi,
-                           double* psi, long long n0, long long n1, hipStream_t s) {
+hipError_t launch_radial_t(const RadialDesc* descs, const double* ctab, int count, size_t bytes,
+                           double* phi, double* psi, long long n0, long long n1, hipStream_t s) {
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)radial_kernel<NPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((radial_kernel<NPT>), dim3(count), dim3(RAD_THREADS), bytes, s, descs, phi,
-                       psi, n0, n1);
+    hipLaunchKernelGGL((radial_kernel<NPT>), dim3(count), dim3(RAD_THREADS), bytes, s, descs, ctab,
+                       phi, psi, n0, n1);
     return hipGetLastError();
 }
 
@@ -181,18 +189,18 @@ hipError_t launch_radial_t(const RadialDesc* descs, int count, size_t bytes, dou
 
 size_t radial_lds_bytes(int max_m) { return (size_t)(2 * (max_m + 4)) * sizeof(double); }
 
-int launch_radial(const RadialDesc* descs, int count, int max_m, double* phi, double* psi,
-                  long long n0, long long n1, void* stream) {
+int launch_radial(const RadialDesc* descs, const double* ctab, int count, int max_m, double* phi,
+                  double* psi, long long n0, long long n1, void* stream) {
     if (count <= 0) return 0;
     const size_t bytes = radial_lds_bytes(max_m);
     hipStream_t s = (hipStream_t)stream;
     const int npt = (max_m + RAD_THREADS - 1) / RAD_THREADS;
     hipError_t e;
-    if (npt <= 1) e = launch_radial_t<1>(descs, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 2) e = launch_radial_t<2>(descs, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 4) e = launch_radial_t<4>(descs, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 8) e = launch_radial_t<8>(descs, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 11) e = launch_radial_t<11>(descs, count, bytes, phi, psi, n0, n1, s);
+    if (npt <= 1) e = launch_radial_t<1>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 2) e = launch_radial_t<2>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 4) e = launch_radial_t<4>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 8) e = launch_radial_t<8>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt <= 11) e = launch_radial_t<11>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
     else return (int)hipErrorInvalidValue;
     return (int)e;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -281,22 +282,29 @@ size_t solve_footprint(const hb_config& c, int scheme, long long steps) {
            (size_t)ctab_capacity(steps, 0) * 4 * sizeof(double);
 }
 
-int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
-    s.cfg = c;
-    s.L = plan_layout(c, scheme);
-    for (int d = 0; d < 3; ++d) s.h[d] = (c.hi[d] - c.lo[d]) / c.n[d];
+// zero a solve's whole allocation on `stream` (the halo then stays zero for
+// the life of the solve) and, with HB_DEBUG_POISON, fill every stored cell
+// outside the interior and its halo with NaN
+int solve_clear(Solve& s, hipStream_t stream) {
     const size_t fb = field_bytes(s.L);
-    const size_t total = fb * (size_t)s.L.nfields;
-    HB_TRY(dev_alloc((void**)&s.mem, total, "solve state", stream));
-    // zero everything once: the halo stays zero for the life of the solve
-    HIP_TRY(hipMemsetAsync(s.mem, 0, total, stream));
-    if (c.flags & HB_DEBUG_POISON) {
+    HIP_TRY(hipMemsetAsync(s.mem, 0, fb * (size_t)s.L.nfields, stream));
+    if (s.cfg.flags & HB_DEBUG_POISON) {
         const long long corner = s.L.origin_off - 2 * s.L.sz - 2 * s.L.sy - 2;
         for (int k = 0; k < s.L.nfields; ++k)
             HB_TRY(from_hip(launch_poison(s.mem + fb * (size_t)k, s.L.field_cells, (int)s.L.esz, s.L.cs,
                                           corner, s.L.sy, s.L.sz, s.L.nx, s.L.nz, stream),
                             "poison"));
     }
+    return HB_OK;
+}
+
+// configuration, layout and field views of a solve over its allocation
+void solve_views(Solve& s, const hb_config& c, int scheme) {
+    s.cfg = c;
+    s.L = plan_layout(c, scheme);
+    for (int d = 0; d < 3; ++d) s.h[d] = (c.hi[d] - c.lo[d]) / c.n[d];
+    for (void*& v : s.f) v = nullptr;
+    const size_t fb = field_bytes(s.L);
     const size_t org = (size_t)s.L.origin_off * s.L.cell_bytes();
     if (s.L.cs > 1) {
         for (int par = 0; par < 2; ++par) {
@@ -308,7 +316,13 @@ int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
         for (int k = 0; k < 9; ++k)
             if (field_used(k, c.precision, scheme)) s.f[k] = s.mem + fb * (size_t)slot++ + org;
     }
-    return HB_OK;
+}
+
+int solve_alloc(Solve& s, const hb_config& c, int scheme, hipStream_t stream) {
+    const Layout L = plan_layout(c, scheme);
+    HB_TRY(dev_alloc((void**)&s.mem, field_bytes(L) * (size_t)L.nfields, "solve state", stream));
+    solve_views(s, c, scheme);
+    return solve_clear(s, stream);
 }
 
 // c(t) = inv_L2 exp(-2 t) at the stage times t_n, t_n + dt/2, t_n + dt/2,
@@ -473,6 +487,49 @@ int default_zc(const Layout& L, int by) {
     return (int)std::max<long long>(1, zc);
 }
 
+// Pinned host staging for asynchronous uploads: a buffer from hipHostMalloc
+// (grown on demand) and an event recorded after the last copy that read or
+// wrote it, so it is refilled only once that copy has finished (a wait on
+// the copy alone, not on the stream's kernels).
+struct Staging {
+    void* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t used = nullptr;
+    ~Staging() { release(); }
+    void release() {
+        if (used) (void)hipEventSynchronize(used);
+        if (buf) (void)hipHostFree(buf);
+        if (used) (void)hipEventDestroy(used);
+        buf = nullptr;
+        used = nullptr;
+        cap = 0;
+    }
+    // a buffer of at least `bytes` bytes that no pending copy uses
+    int get(size_t bytes, void** out) {
+        if (used) HIP_TRY(hipEventSynchronize(used));
+        if (bytes > cap) {
+            if (buf) (void)hipHostFree(buf);
+            buf = nullptr;
+            cap = 0;
+            const size_t want = std::max<size_t>(bytes, 1 << 16);
+            if (hipHostMalloc(&buf, want, hipHostMallocDefault) != hipSuccess) {
+                buf = nullptr;
+                (void)hipGetLastError();
+                return fail(HB_E_NOMEM, "pinned staging (%zu bytes): host allocation failed", want);
+            }
+            cap = want;
+        }
+        if (!used) HIP_TRY(hipEventCreateWithFlags(&used, hipEventDisableTiming));
+        *out = buf;
+        return HB_OK;
+    }
+    // mark the copies enqueued on `stream` so far as the buffer's last use
+    int mark(hipStream_t stream) {
+        HIP_TRY(hipEventRecord(used, stream));
+        return HB_OK;
+    }
+};
+
 struct Group {
     int prec = HB_F64;
     int scheme = SCHEME_STEP;  // 1 whole-step, 2 stage-pair or 4 per-stage launches per step
@@ -488,6 +545,7 @@ struct Group {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_k = 0;
+    Staging staging;  // descriptor and tile-table uploads
 
     ~Group() { release(); }
     void drop_graph() {
@@ -499,6 +557,7 @@ struct Group {
     }
     void release() {
         drop_graph();
+        staging.release();
         dev_free(d_desc);
         dev_free(d_tiles);
         d_desc = nullptr;
@@ -602,7 +661,12 @@ void make_tiles(const Solve& s, int solve_index, int scheme, int by, int zc_req,
             }
 }
 
-// (re)upload descriptors and the tile table; invalidates any captured graph
+// (re)upload descriptors and the tile table; invalidates any captured graph.
+// The upload is ordered on `stream` after the work already enqueued there
+// (which may still read the old tables) and does not wait for it: the host
+// copies go through the group's pinned staging.  Device tables grow by
+// doubling, so a growing group rarely replaces them (a replacement frees
+// the old table, which waits for the device).
 int group_rebuild(Group& g, hipStream_t stream) {
     g.drop_graph();
     std::vector<SolveDesc> descs;
@@ -611,27 +675,35 @@ int group_rebuild(Group& g, hipStream_t stream) {
         descs.push_back(make_desc(*g.members[i]));
         make_tiles(*g.members[i], (int)i, g.scheme, g.by, g.zc, (int)g.members.size(), tiles);
     }
-    HIP_TRY(hipStreamSynchronize(stream));
     if ((int)descs.size() > g.desc_cap) {
+        const int old_cap = g.desc_cap;
         dev_free(g.d_desc);
         g.d_desc = nullptr;
         g.desc_cap = 0;
-        const int cap = std::max<int>(1, (int)descs.size());
+        const int cap = std::max<int>(std::max<int>(1, (int)descs.size()), 2 * old_cap);
         HB_TRY(dev_alloc((void**)&g.d_desc, cap * sizeof(SolveDesc), "descriptors", stream));
         g.desc_cap = cap;
     }
     if ((int)tiles.size() > g.tile_cap) {
+        const int old_cap = g.tile_cap;
         dev_free(g.d_tiles);
         g.d_tiles = nullptr;
         g.tile_cap = 0;
-        const int cap = std::max<int>(1, (int)tiles.size());
+        const int cap = std::max<int>(std::max<int>(1, (int)tiles.size()), 2 * old_cap);
         HB_TRY(dev_alloc((void**)&g.d_tiles, cap * sizeof(Tile), "tile table", stream));
         g.tile_cap = cap;
     }
-    if (!descs.empty())
-        HIP_TRY(hipMemcpy(g.d_desc, descs.data(), descs.size() * sizeof(SolveDesc), hipMemcpyHostToDevice));
-    if (!tiles.empty())
-        HIP_TRY(hipMemcpy(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    const size_t db = descs.size() * sizeof(SolveDesc), tb = tiles.size() * sizeof(Tile);
+    const size_t toff = (size_t)round_up((long long)db, 256);
+    if (db + tb > 0) {
+        void* h = nullptr;
+        HB_TRY(g.staging.get(toff + tb, &h));
+        if (db) std::memcpy(h, descs.data(), db);
+        if (tb) std::memcpy((char*)h + toff, tiles.data(), tb);
+        if (db) HIP_TRY(hipMemcpyAsync(g.d_desc, h, db, hipMemcpyHostToDevice, stream));
+        if (tb) HIP_TRY(hipMemcpyAsync(g.d_tiles, (char*)h + toff, tb, hipMemcpyHostToDevice, stream));
+        HB_TRY(g.staging.mark(stream));
+    }
     g.ntiles = (int)tiles.size();
     g.periodic = false;
     for (Solve* m : g.members) g.periodic = g.periodic || (m->cfg.flags & HB_BC_PERIODIC);
@@ -757,10 +829,14 @@ struct hb_solver {
     double* d_partials = nullptr;
     double* d_diag = nullptr;
     int nparts = 0;
+    unsigned* d_labels = nullptr;            // bubble count: one label per interior point
+    unsigned long long* d_counts = nullptr;  // ... and its two set counts
     ~hb_solver() {
         g.release();
         dev_free(d_partials);
         dev_free(d_diag);
+        dev_free(d_labels);
+        dev_free(d_counts);
         s.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -937,6 +1013,32 @@ int hb_diagnostics(hb_solver* h, hb_diag* out) {
     return HB_OK;
 }
 
+int hb_bubbles(hb_solver* h, double eps, int64_t* negative_sets, int64_t* positive_sets) {
+    if (!h || !negative_sets || !positive_sets) return fail(HB_E_ARG, "NULL argument");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(HB_E_ARG, "eps must be finite and >= 0");
+    Solve& s = *h->s;
+    if (!s.has_initial) return fail(HB_E_STATE, "no initial data");
+    const long long pts = (long long)s.L.nx * s.L.ny * s.L.nz;
+    if (pts >= (long long)0xffffffffLL)
+        return fail(HB_E_ARG, "bubble count: %lld interior points (at most 2^32 - 2)", pts);
+    if (!h->built) HB_TRY(solver_rebuild(h));
+    if (!h->d_labels) {
+        HB_TRY(dev_alloc((void**)&h->d_labels, (size_t)pts * sizeof(unsigned), "bubble labels", h->stream));
+    }
+    if (!h->d_counts) {
+        HB_TRY(dev_alloc((void**)&h->d_counts, 2 * sizeof(unsigned long long), "bubble counts", h->stream));
+    }
+    HB_TRY(from_hip(launch_bubbles(s.prec(), h->g.d_desc, (int)(s.nstep & 1), eps, pts, h->d_labels,
+                                   h->d_counts, h->stream),
+                    "bubbles"));
+    unsigned long long v[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(v, h->d_counts, sizeof v, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *negative_sets = (int64_t)v[0];
+    *positive_sets = (int64_t)v[1];
+    return HB_OK;
+}
+
 int hb_set_tiling(hb_solver* h, int by, int zc) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
     if (!valid_by(by, h->g.scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11, whole-step scheme)");
@@ -960,15 +1062,36 @@ int hb_destroy(hb_solver* h) {
 
 namespace {
 
-std::string tune_key(const Solve& s, int nmembers) {
+// Cache key of a launch group: device architecture, precision, scheme and
+// the grids it holds.  One solve: its grid ("NXxNYxNZ|m1"); a batch: the
+// member count and a 64-bit FNV-1a hash of the members' sorted grid list,
+// so batches with the same mix of sizes share an entry and others do not.
+std::string tune_key(const Group& g) {
     hipDeviceProp_t p;
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::string name = "unknown";
     if (hipGetDeviceProperties(&p, dev) == hipSuccess) name = p.gcnArchName;
+    const Solve& s = *g.members[0];
     std::ostringstream k;
-    k << name << "|prec" << s.cfg.precision << "|scheme" << scheme_of(s.cfg.flags) << "|" << s.L.nx << "x" << s.L.ny << "x" << s.L.nz << "|m"
-      << nmembers;
+    k << name << "|prec" << s.cfg.precision << "|scheme" << scheme_of(s.cfg.flags) << "|";
+    if (g.members.size() == 1) {
+        k << s.L.nx << "x" << s.L.ny << "x" << s.L.nz << "|m1";
+    } else {
+        std::vector<std::array<int, 3>> dims;
+        for (const Solve* m : g.members) dims.push_back({m->L.nx, m->L.ny, m->L.nz});
+        std::sort(dims.begin(), dims.end());
+        unsigned long long hsh = 1469598103934665603ULL;
+        for (const auto& d : dims)
+            for (int v : d)
+                for (int b = 0; b < 4; ++b) {
+                    hsh ^= (unsigned long long)((unsigned)v >> (8 * b) & 0xffu);
+                    hsh *= 1099511628211ULL;
+                }
+        char hex[17];
+        snprintf(hex, sizeof hex, "%016llx", hsh);
+        k << "batch" << hex << "|m" << g.members.size();
+    }
     return k.str();
 }
 
@@ -1051,8 +1174,7 @@ int snapshot_restore(Group& g, Snapshot& snap, const std::vector<long long>& nst
 
 int group_autotune(Group& g, int trial_steps, hipStream_t stream, int* best_by, int* best_zc) {
     if (g.members.empty()) return fail(HB_E_STATE, "nothing to tune");
-    const Solve& s0 = *g.members[0];
-    const std::string key = tune_key(s0, (int)g.members.size());
+    const std::string key = tune_key(g);
     int cb = 0, cz = 0;
     if (cache_lookup(key, &cb, &cz)) {
         g.by = cb;
@@ -1233,6 +1355,24 @@ int hb_batch_set_tiling(hb_batch* b, int by, int zc) {
     return HB_OK;
 }
 
+int hb_batch_autotune(hb_batch* b, int trial_steps, int* by, int* zc) {
+    if (!b) return fail(HB_E_ARG, "batch is NULL");
+    if (trial_steps < 1) return fail(HB_E_ARG, "trial_steps must be >= 1");
+    for (auto& s : b->solves)
+        if (!s->has_initial) return fail(HB_E_STATE, "a solve has no initial data");
+    for (int p = 0; p < 2; ++p) {
+        Group& g = b->groups[p];
+        int bb = -1, bz = -1;
+        if (!g.members.empty()) HB_TRY(group_autotune(g, trial_steps, b->stream, &bb, &bz));
+        if (by) by[p] = bb;
+        if (zc) zc[p] = bz;
+    }
+    // each group was rebuilt with its choice; targets were restored, so the
+    // next hb_batch_step sets them again
+    b->built = true;
+    return HB_OK;
+}
+
 int hb_batch_destroy(hb_batch* b) {
     if (!b) return HB_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1251,20 +1391,115 @@ struct hb_pool {
         bool busy = false;
         bool done = false;
         bool reported = false;
+        bool joined = false;           // the compute stream has waited for `ready`
+        bool has_fin = false;
+        hipEvent_t ready = nullptr;    // admission transfer complete (copy stream)
+        hipEvent_t fin = nullptr;      // compute-stream point after its last step
+    };
+    // a released solve, kept for an admission of the same footprint
+    struct Spare {
+        std::unique_ptr<Solve> s;
+        size_t bytes = 0;
+        hipEvent_t retired = nullptr;  // compute-stream point after which nothing touches it
     };
     std::vector<Slot> slots;
-    size_t budget = 0, in_use = 0;
+    std::vector<Spare> spares;
+    size_t budget = 0, in_use = 0, spare_bytes = 0;
     Group groups[2];
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // compute: the step launches
+    hipStream_t xfer = nullptr;    // copies: admissions and reads of finished solves
     bool own_stream = false;
     bool dirty = true;
+    Staging hst;                   // pinned host staging of the copy stream
+    void* dstage = nullptr;        // device staging (used in copy-stream order)
+    size_t dstage_cap = 0;
     ~hb_pool() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (xfer) (void)hipStreamSynchronize(xfer);
         groups[0].release();
         groups[1].release();
+        for (auto& sl : slots) {
+            if (sl.ready) (void)hipEventDestroy(sl.ready);
+            if (sl.fin) (void)hipEventDestroy(sl.fin);
+        }
+        for (auto& sp : spares)
+            if (sp.retired) (void)hipEventDestroy(sp.retired);
         slots.clear();
+        spares.clear();
+        hst.release();
+        dev_free(dstage);
+        if (xfer) (void)hipStreamDestroy(xfer);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
+    // device staging of at least `bytes` (its previous contents are used only
+    // by copy-stream work, which later copy-stream work follows)
+    int device_staging(size_t bytes, void** out) {
+        if (bytes > dstage_cap) {
+            dev_free(dstage);  // waits for the copy stream's use of it
+            dstage = nullptr;
+            dstage_cap = 0;
+            const size_t want = std::max<size_t>(bytes, 1 << 20);
+            HB_TRY(dev_alloc(&dstage, want, "pool staging", xfer));
+            dstage_cap = want;
+        }
+        *out = dstage;
+        return HB_OK;
+    }
 };
+
+namespace {
+
+int ensure_event(hipEvent_t* e) {
+    if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return HB_OK;
+}
+
+// Admission transfer of one solve on the copy stream: zero its allocation,
+// upload its coefficient table and its initial state (host inputs through
+// the pinned staging).  Nothing here waits for the compute stream.
+int pool_upload(hb_pool* p, Solve& s, const void* phi0, const void* phi1, int mem, int dtype) {
+    if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(HB_E_ARG, "bad dtype");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    HB_TRY(solve_clear(s, p->xfer));
+    const long long cnt = (long long)s.L.nx * s.L.ny * s.L.nz;
+    const size_t vb = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
+    const size_t tb = (size_t)s.ctab_steps * 4 * sizeof(double);
+    const size_t voff = (size_t)round_up((long long)tb, 256);
+    const int nsrc = mem == HB_HOST ? (phi1 ? 2 : 1) : 0;
+    void* h = nullptr;
+    HB_TRY(p->hst.get(voff + vb * (size_t)nsrc, &h));
+    std::vector<double> tab;
+    try {
+        fill_ctab(s.cfg, 0, s.ctab_steps, tab);
+    } catch (const std::bad_alloc&) {
+        return fail(HB_E_NOMEM, "coefficient table: host allocation failed");
+    }
+    std::memcpy(h, tab.data(), tb);
+    HIP_TRY(hipMemcpyAsync(s.ctab, h, tb, hipMemcpyHostToDevice, p->xfer));
+    const void* src[2] = {phi0, phi1};
+    void* hi[2] = {s.f[0], s.f[2]};
+    float* lo[2] = {s.lo_view(0, 0), s.lo_view(1, 0)};
+    void* dst = nullptr;
+    if (nsrc) HB_TRY(p->device_staging(vb * (size_t)nsrc, &dst));
+    for (int k = 0; k < 2; ++k) {
+        const void* d = src[k];
+        if (src[k] && mem == HB_HOST) {
+            char* hk = (char*)h + voff + vb * (size_t)k;
+            std::memcpy(hk, src[k], vb);
+            char* dk = (char*)dst + vb * (size_t)k;
+            HIP_TRY(hipMemcpyAsync(dk, hk, vb, hipMemcpyHostToDevice, p->xfer));
+            d = dk;
+        }
+        if (k == 1 && !src[1]) continue;  // psi stays zero from the clear
+        HB_TRY(from_hip(launch_unpack(s.prec(), dtype, d, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, s.L.cs,
+                                      hi[k], lo[k], p->xfer),
+                        "unpack"));
+    }
+    HB_TRY(p->hst.mark(p->xfer));
+    return HB_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1283,6 +1518,7 @@ int hb_pool_create(size_t hbm_budget, int max_slots, void* stream, hb_pool** out
         HIP_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
         p->own_stream = true;
     }
+    HIP_TRY(hipStreamCreateWithFlags(&p->xfer, hipStreamNonBlocking));
     p->groups[0].prec = HB_F64;
     p->groups[1].prec = HB_F32C;
     for (Group& g : p->groups) g.by = DEFAULT_BY;  // whole-step scheme: 64 x 16 regions
@@ -1299,6 +1535,8 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
     if (steps < 0 || steps > MAX_STEPS) return fail(HB_E_ARG, "steps must be in [0, 2^40]");
     if (scheme_of(cfg->flags) != SCHEME_STEP)
         return fail(HB_E_ARG, "pool solves use the whole-step kernel (no HB_PAIRWISE/HB_STAGEWISE)");
+    if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(HB_E_ARG, "bad dtype");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
     const size_t need = solve_footprint(*cfg, SCHEME_STEP, steps + 1);
     int free_slot = -1;
     for (size_t i = 0; i < p->slots.size(); ++i)
@@ -1307,20 +1545,74 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
             break;
         }
     if (free_slot < 0) return fail(HB_E_BUSY, "no free slot");
-    if (need > p->budget - p->in_use) return fail(HB_E_BUSY, "HBM budget exhausted");
-    auto s = std::make_unique<Solve>();
-    HB_TRY(solve_alloc(*s, *cfg, SCHEME_STEP, p->stream));
-    HB_TRY(ensure_ctab(*s, steps + 1, p->stream, nullptr));
-    HB_TRY(upload_state(*s, 0, 2, phi0, phi1, mem, dtype, p->stream));
+    // a released solve of the same footprint is taken over (its allocation
+    // and coefficient table fit this configuration exactly)
+    int reuse = -1;
+    for (size_t i = 0; i < p->spares.size(); ++i)
+        if (p->spares[i].bytes == need) {
+            reuse = (int)i;
+            break;
+        }
+    // spares count against the budget (in_use + spare_bytes <= budget):
+    // without one to take over, give spares back, oldest first, until the
+    // solve fits (freeing a block waits for the device)
+    if (reuse < 0) {
+        size_t k = 0;
+        while (need + p->in_use + p->spare_bytes > p->budget && k < p->spares.size()) {
+            hb_pool::Spare& sp = p->spares[k];
+            if (sp.retired) {
+                (void)hipEventSynchronize(sp.retired);
+                (void)hipEventDestroy(sp.retired);
+            }
+            p->spare_bytes -= sp.bytes;
+            sp.s.reset();
+            p->spares.erase(p->spares.begin() + (long)k);
+        }
+    }
+    if (p->in_use + (p->spare_bytes - (reuse >= 0 ? need : 0)) + need > p->budget)
+        return fail(HB_E_BUSY, "HBM budget exhausted");
+    std::unique_ptr<Solve> s;
+    if (reuse >= 0) {
+        hb_pool::Spare sp = std::move(p->spares[reuse]);
+        p->spares.erase(p->spares.begin() + reuse);
+        p->spare_bytes -= sp.bytes;
+        s = std::move(sp.s);
+        // the copy stream rewrites the memory only after the compute stream
+        // has passed every launch that could still touch it
+        hipError_t e = sp.retired ? hipStreamWaitEvent(p->xfer, sp.retired, 0) : hipSuccess;
+        if (sp.retired) (void)hipEventDestroy(sp.retired);
+        if (e != hipSuccess) return fail(HB_E_HIP, "pool reuse wait: %s", hipGetErrorString(e));
+        solve_views(*s, *cfg, SCHEME_STEP);
+    } else {
+        s = std::make_unique<Solve>();
+        const Layout L = plan_layout(*cfg, SCHEME_STEP);
+        HB_TRY(dev_alloc((void**)&s->mem, field_bytes(L) * (size_t)L.nfields, "solve state", p->xfer));
+        solve_views(*s, *cfg, SCHEME_STEP);
+        const long long cap = ctab_capacity(steps + 1, 0);
+        HB_TRY(dev_alloc((void**)&s->ctab, (size_t)cap * 4 * sizeof(double), "coefficient table", p->xfer));
+        s->ctab_steps = cap;
+    }
+    if (mem == HB_DEVICE) {
+        // device inputs are read in the pool stream's order
+        hb_pool::Slot& sl0 = p->slots[free_slot];
+        HB_TRY(ensure_event(&sl0.ready));
+        HIP_TRY(hipEventRecord(sl0.ready, p->stream));
+        HIP_TRY(hipStreamWaitEvent(p->xfer, sl0.ready, 0));
+    }
+    HB_TRY(pool_upload(p, *s, phi0, phi1, mem, dtype));
     s->nstep = 0;
     s->target = steps;
     s->has_initial = true;
     hb_pool::Slot& sl = p->slots[free_slot];
+    HB_TRY(ensure_event(&sl.ready));
+    HIP_TRY(hipEventRecord(sl.ready, p->xfer));
     sl.s = std::move(s);
     sl.bytes = need;
     sl.busy = true;
     sl.done = (steps == 0);
     sl.reported = false;
+    sl.joined = false;
+    sl.has_fin = false;
     p->in_use += need;
     p->dirty = true;
     *slot = free_slot;
@@ -1330,7 +1622,14 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
 static int pool_rebuild(hb_pool* p) {
     for (Group& g : p->groups) g.members.clear();
     for (auto& sl : p->slots)
-        if (sl.busy && !sl.done) p->groups[sl.s->prec()].members.push_back(sl.s.get());
+        if (sl.busy && !sl.done) {
+            if (!sl.joined) {
+                // the compute stream waits for this solve's admission copies only
+                HIP_TRY(hipStreamWaitEvent(p->stream, sl.ready, 0));
+                sl.joined = true;
+            }
+            p->groups[sl.s->prec()].members.push_back(sl.s.get());
+        }
     for (Group& g : p->groups) {
         if (g.members.empty()) {
             g.drop_graph();
@@ -1343,18 +1642,27 @@ static int pool_rebuild(hb_pool* p) {
     return HB_OK;
 }
 
+// mark a slot finished: its last step is behind everything enqueued so far
+static int pool_finish(hb_pool* p, hb_pool::Slot& sl) {
+    sl.done = true;
+    HB_TRY(ensure_event(&sl.fin));
+    HIP_TRY(hipEventRecord(sl.fin, p->stream));
+    sl.has_fin = true;
+    p->dirty = true;
+    return HB_OK;
+}
+
 int hb_pool_advance(hb_pool* p, int k) {
     if (!p) return fail(HB_E_ARG, "pool is NULL");
     if (k < 0) return fail(HB_E_ARG, "k must be >= 0");
-    if (p->dirty) HB_TRY(pool_rebuild(p));
-    for (Group& g : p->groups) HB_TRY(group_step(g, k, false, p->stream));
-    bool finished = false;
+    // while the active set is the one of the previous advance, steps replay
+    // the group's captured graph; a changed set is rebuilt and launched
+    // directly this time
+    const bool changed = p->dirty;
+    if (changed) HB_TRY(pool_rebuild(p));
+    for (Group& g : p->groups) HB_TRY(group_step(g, k, !changed, p->stream));
     for (auto& sl : p->slots)
-        if (sl.busy && !sl.done && sl.s->nstep >= sl.s->target) {
-            sl.done = true;
-            finished = true;
-        }
-    if (finished) p->dirty = true;
+        if (sl.busy && !sl.done && sl.s->nstep >= sl.s->target) HB_TRY(pool_finish(p, sl));
     return HB_OK;
 }
 
@@ -1417,8 +1725,7 @@ int hb_pool_check(hb_pool* p, int* failed, int cap, int* nfailed) {
         for (size_t i = 0; i < p->slots.size(); ++i) {
             auto& sl = p->slots[i];
             if (!sl.busy || sl.s.get() != order[m]) continue;
-            sl.done = true;  // stops stepping; hb_pool_poll reports it
-            p->dirty = true;
+            HB_TRY(pool_finish(p, sl));  // stops stepping; hb_pool_poll reports it
             if (n < cap) failed[n] = (int)i;
             ++n;
         }
@@ -1440,20 +1747,83 @@ int hb_pool_stats(const hb_pool* p, int* active, size_t* in_use) {
 int hb_pool_read(hb_pool* p, int slot, void* phi, void* phi_t, int mem, int dtype) {
     if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot].busy)
         return fail(HB_E_ARG, "bad slot");
-    return download_state(*p->slots[slot].s, phi, phi_t, mem, dtype, p->stream);
+    auto& sl = p->slots[slot];
+    if (!sl.done || !sl.has_fin) {
+        // not finished by a step (still running, or admitted with 0 steps):
+        // read in the compute stream's order, after the admission copies
+        if (!sl.joined) {
+            HIP_TRY(hipStreamWaitEvent(p->stream, sl.ready, 0));
+            sl.joined = true;
+        }
+        return download_state(*sl.s, phi, phi_t, mem, dtype, p->stream);
+    }
+    if (dtype != HB_DTYPE_F64 && dtype != HB_DTYPE_F32) return fail(HB_E_ARG, "bad dtype");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    // a finished solve is copied out on the copy stream, after its last step
+    // and without waiting for the steps of the others enqueued since
+    Solve& s = *sl.s;
+    HIP_TRY(hipStreamWaitEvent(p->xfer, sl.fin, 0));
+    const int par = (int)(s.nstep & 1);
+    const long long cnt = (long long)s.L.nx * s.L.ny * s.L.nz;
+    const size_t vb = (size_t)cnt * (dtype == HB_DTYPE_F64 ? 8 : 4);
+    void* dst[2] = {phi, phi_t};
+    const void* hi[2] = {s.f[0 + par], s.f[2 + par]};
+    const float* lo[2] = {s.lo_view(0, par), s.lo_view(1, par)};
+    if (mem == HB_DEVICE) {
+        for (int k = 0; k < 2; ++k)
+            if (dst[k])
+                HB_TRY(from_hip(launch_pack(s.prec(), dtype, dst[k], s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz,
+                                            s.L.cs, hi[k], lo[k], p->xfer),
+                                "pack"));
+        HIP_TRY(hipStreamSynchronize(p->xfer));
+        return HB_OK;
+    }
+    const int nout = (phi ? 1 : 0) + (phi_t ? 1 : 0);
+    if (nout == 0) return HB_OK;
+    void* d = nullptr;
+    void* h = nullptr;
+    HB_TRY(p->device_staging(vb * (size_t)nout, &d));
+    HB_TRY(p->hst.get(vb * (size_t)nout, &h));
+    int j = 0;
+    for (int k = 0; k < 2; ++k) {
+        if (!dst[k]) continue;
+        char* dk = (char*)d + vb * (size_t)j;
+        HB_TRY(from_hip(launch_pack(s.prec(), dtype, dk, s.L.nx, s.L.ny, s.L.nz, s.L.sy, s.L.sz, s.L.cs,
+                                    hi[k], lo[k], p->xfer),
+                        "pack"));
+        HIP_TRY(hipMemcpyAsync((char*)h + vb * (size_t)j, dk, vb, hipMemcpyDeviceToHost, p->xfer));
+        ++j;
+    }
+    HB_TRY(p->hst.mark(p->xfer));
+    HIP_TRY(hipStreamSynchronize(p->xfer));
+    j = 0;
+    for (int k = 0; k < 2; ++k)
+        if (dst[k]) std::memcpy(dst[k], (char*)h + vb * (size_t)j++, vb);
+    return HB_OK;
 }
 
 int hb_pool_release(hb_pool* p, int slot) {
     if (!p || slot < 0 || slot >= (int)p->slots.size() || !p->slots[slot].busy)
         return fail(HB_E_ARG, "bad slot");
-    HIP_TRY(hipStreamSynchronize(p->stream));
     auto& sl = p->slots[slot];
     const bool active = !sl.done;
+    // the solve is kept for a later admission of the same footprint; it may
+    // be rewritten once the compute stream has passed what is enqueued now
+    hb_pool::Spare sp;
+    HB_TRY(ensure_event(&sp.retired));
+    HIP_TRY(hipEventRecord(sp.retired, p->stream));
+    // a join that never happened still orders the compute stream after the
+    // admission copies (they precede every later copy-stream use anyway)
+    sp.s = std::move(sl.s);
+    sp.bytes = sl.bytes;
     p->in_use -= sl.bytes;
-    sl.s.reset();
+    p->spare_bytes += sl.bytes;
+    p->spares.push_back(std::move(sp));
     sl.busy = false;
     sl.done = false;
     sl.reported = false;
+    sl.joined = false;
+    sl.has_fin = false;
     sl.bytes = 0;
     if (active) p->dirty = true;
     return HB_OK;
@@ -1461,7 +1831,6 @@ int hb_pool_release(hb_pool* p, int slot) {
 
 int hb_pool_destroy(hb_pool* p) {
     if (!p) return HB_OK;
-    if (p->stream) (void)hipStreamSynchronize(p->stream);
     delete p;
     return HB_OK;
 }
@@ -1511,24 +1880,35 @@ extern "C" int hb_probe_bandwidth(int kind, size_t bytes_per_array, int iters, d
 
 // ---- batched radial solves ------------------------------------------------------
 
-constexpr long long RADIAL_CHUNK = 1LL << 16;
+namespace {
 
-extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi,
-                               int mem, void* stream) {
-    g_last_error.clear();
-    if (count < 0 || (count > 0 && (!cfgs || !phi || !psi)))
-        return fail(HB_E_ARG, "bad radial batch arguments");
-    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
-    if (count == 0) return HB_OK;
-    std::vector<RadialDesc> descs(count);
+constexpr long long RADIAL_CHUNK = 1LL << 16;
+// c(t) table of one launch: at most this many doubles (the launch length
+// shrinks when many solves have distinct (t0, dt, inv_L2))
+constexpr long long RADIAL_TABLE_DOUBLES = 4LL << 20;
+
+// A validated radial batch: descriptors, and the distinct (t0, dt, inv_L2)
+// of its solves, whose c(t) rows the launches share.
+struct RadialPlan {
+    std::vector<RadialDesc> descs;
+    std::vector<int> key_of;                     // per solve: its (t0, dt, inv_L2)
+    std::vector<std::array<double, 3>> keys;     // t0, dt, inv_L2
+    std::vector<long long> key_steps;            // most steps of any solve of the key
     long long total = 0, max_steps = 0;
     int max_m = 0;
+};
+
+int radial_plan(int count, const hb_radial_config* cfgs, RadialPlan& p) {
+    p.descs.assign(count, RadialDesc{});
+    p.key_of.assign(count, 0);
+    std::map<std::array<double, 3>, int> index;
     for (int i = 0; i < count; ++i) {
         const hb_radial_config& c = cfgs[i];
         if (c.m < 1 || c.m > HB_RADIAL_MAX_NODES)
             return fail(HB_E_ARG, "radial solve %d: m = %d outside [1, %d]", i, c.m, HB_RADIAL_MAX_NODES);
         if (!(c.dr > 0) || !(c.dt > 0) || !std::isfinite(c.dr) || !std::isfinite(c.dt) || c.steps < 0)
             return fail(HB_E_ARG, "radial solve %d: need dr > 0, dt > 0, steps >= 0", i);
+        if (c.steps > MAX_STEPS) return fail(HB_E_ARG, "radial solve %d: steps beyond 2^40", i);
         if (!std::isfinite(c.mu2) || !std::isfinite(c.lambda) || !std::isfinite(c.inv_L2) ||
             !std::isfinite(c.t0) || c.inv_L2 < 0)
             return fail(HB_E_ARG, "radial solve %d: coefficients must be finite (inv_L2 >= 0)", i);
@@ -1537,9 +1917,9 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
             if (c.dt * std::sqrt(c0 * 16.0 / (c.dr * c.dr)) > 2.0 * std::sqrt(2.0))
                 return fail(HB_E_CFL, "radial solve %d: dt = %g beyond the stability limit", i, c.dt);
         }
-        RadialDesc& d = descs[i];
+        RadialDesc& d = p.descs[i];
         std::memset(&d, 0, sizeof d);
-        d.offset = total;
+        d.offset = p.total;
         d.steps = c.steps;
         d.m = c.m;
         d.dr = c.dr;
@@ -1548,17 +1928,93 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
         d.inv_L2 = c.inv_L2;
         d.t0 = c.t0;
         d.dt = c.dt;
-        total += c.m;
-        max_m = std::max(max_m, c.m);
-        max_steps = std::max<long long>(max_steps, c.steps);
+        const std::array<double, 3> key = {c.t0, c.dt, c.inv_L2};
+        auto it = index.find(key);
+        if (it == index.end()) {
+            it = index.emplace(key, (int)p.keys.size()).first;
+            p.keys.push_back(key);
+            p.key_steps.push_back(0);
+        }
+        p.key_of[i] = it->second;
+        p.key_steps[it->second] = std::max<long long>(p.key_steps[it->second], c.steps);
+        p.total += c.m;
+        p.max_m = std::max(p.max_m, c.m);
+        p.max_steps = std::max<long long>(p.max_steps, c.steps);
     }
+    return HB_OK;
+}
+
+// steps per launch: at most RADIAL_CHUNK, and few enough that every key's
+// rows fit `table_doubles` (0 if not even one step fits)
+long long radial_chunk(const RadialPlan& p, long long table_doubles) {
+    const long long per_step = 3 * (long long)std::max<size_t>(1, p.keys.size());
+    return std::min<long long>(RADIAL_CHUNK, table_doubles / per_step);
+}
+
+// Run a planned batch on device state dphi/dpsi with the given descriptor
+// array (descs.size() entries) and c(t) table (>= 3 x chunk x keys doubles).
+// Each launch covers `chunk` steps of every solve; its table rows are filled
+// on the host (the stage times of eq. (rhs) in FP64, as for the 3-D path) and
+// copied before the launch, and the stream is drained after it, so the table
+// can be refilled.  Waits for completion.
+int radial_run(RadialPlan& p, long long chunk, RadialDesc* d_desc, double* d_table, double* dphi,
+               double* dpsi, hipStream_t s) {
+    for (size_t i = 0; i < p.descs.size(); ++i) p.descs[i].ctab = 3 * chunk * p.key_of[i];
+    HIP_TRY(hipMemcpyAsync(d_desc, p.descs.data(), p.descs.size() * sizeof(RadialDesc),
+                           hipMemcpyHostToDevice, s));
+    std::vector<double> table;
+    try {
+        table.assign((size_t)(3 * chunk * (long long)p.keys.size()), 0.0);
+    } catch (const std::bad_alloc&) {
+        return fail(HB_E_NOMEM, "radial coefficient table: host allocation failed");
+    }
+    // launches of at most `chunk` steps each, so no single kernel runs for an
+    // unbounded time (the state goes through memory between them)
+    for (long long n0 = 0; n0 < std::max<long long>(p.max_steps, 1); n0 += chunk) {
+        const long long n1 = n0 + chunk;
+        for (size_t k = 0; k < p.keys.size(); ++k) {
+            const double t0 = p.keys[k][0], dt = p.keys[k][1], il2 = p.keys[k][2];
+            double* row = &table[(size_t)(3 * chunk * (long long)k)];
+            for (long long n = n0; n < std::min(n1, p.key_steps[k]); ++n) {
+                const double t = t0 + (double)n * dt;
+                double* o = row + 3 * (n - n0);
+                o[0] = std::exp(-2.0 * t) * il2;
+                o[1] = std::exp(-2.0 * (t + dt / 2.0)) * il2;
+                o[2] = std::exp(-2.0 * (t + dt)) * il2;
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        HB_TRY(from_hip(launch_radial(d_desc, d_table, (int)p.descs.size(), p.max_m, dphi, dpsi, n0, n1, s),
+                        "radial launch"));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return HB_OK;
+}
+
+}  // namespace
+
+extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi,
+                               int mem, void* stream) {
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!cfgs || !phi || !psi)))
+        return fail(HB_E_ARG, "bad radial batch arguments");
+    if (mem != HB_HOST && mem != HB_DEVICE) return fail(HB_E_ARG, "bad memory kind");
+    if (count == 0) return HB_OK;
+    RadialPlan plan;
+    HB_TRY(radial_plan(count, cfgs, plan));
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = (size_t)total * sizeof(double);
+    const size_t bytes = (size_t)plan.total * sizeof(double);
+    const long long chunk = radial_chunk(plan, RADIAL_TABLE_DOUBLES);
+    if (chunk < 1) return fail(HB_E_ARG, "radial batch: too many distinct (t0, dt, inv_L2)");
+    const long long tab = 3 * std::min(chunk, std::max<long long>(plan.max_steps, 1)) *
+                          (long long)plan.keys.size();
     RadialDesc* d_desc = nullptr;
+    double* d_table = nullptr;
     double* dphi = nullptr;
     double* dpsi = nullptr;
-    int rc = HB_OK;
-    rc = dev_alloc((void**)&d_desc, descs.size() * sizeof(RadialDesc), "radial descriptors", s);
+    int rc = dev_alloc((void**)&d_desc, plan.descs.size() * sizeof(RadialDesc), "radial descriptors", s);
+    if (rc == HB_OK) rc = dev_alloc((void**)&d_table, (size_t)tab * sizeof(double), "radial c(t) table", s);
     if (mem == HB_HOST) {
         if (rc == HB_OK) rc = dev_alloc((void**)&dphi, bytes, "radial state", s);
         if (rc == HB_OK) rc = dev_alloc((void**)&dpsi, bytes, "radial state", s);
@@ -1566,18 +2022,14 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
         dphi = phi;
         dpsi = psi;
     }
-    if (rc == HB_OK)
-        rc = from_hip(hipMemcpyAsync(d_desc, descs.data(), descs.size() * sizeof(RadialDesc),
-                                     hipMemcpyHostToDevice, s), "radial descriptors");
     if (rc == HB_OK && mem == HB_HOST) {
         rc = from_hip(hipMemcpyAsync(dphi, phi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
         if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(dpsi, psi, bytes, hipMemcpyHostToDevice, s), "radial H2D");
     }
-    // launches of at most RADIAL_CHUNK steps each, so no single kernel runs
-    // for an unbounded time (the state goes through memory between them)
-    for (long long n0 = 0; rc == HB_OK && n0 < std::max<long long>(max_steps, 1); n0 += RADIAL_CHUNK)
-        rc = from_hip(launch_radial(d_desc, count, max_m, dphi, dpsi, n0, n0 + RADIAL_CHUNK, s),
-                      "radial launch");
+    // the table holds `chunk` rows per key only when some solve runs that
+    // long: shorter batches use a single launch of max_steps steps
+    if (rc == HB_OK) rc = radial_run(plan, std::min(chunk, std::max<long long>(plan.max_steps, 1)), d_desc,
+                                     d_table, dphi, dpsi, s);
     if (rc == HB_OK && mem == HB_HOST) {
         rc = from_hip(hipMemcpyAsync(phi, dphi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");
         if (rc == HB_OK) rc = from_hip(hipMemcpyAsync(psi, dpsi, bytes, hipMemcpyDeviceToHost, s), "radial D2H");
@@ -1585,6 +2037,7 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     hipError_t e = hipStreamSynchronize(s);
     if (rc == HB_OK && e != hipSuccess) rc = fail(HB_E_HIP, "radial sync: %s", hipGetErrorString(e));
     dev_free(d_desc);
+    dev_free(d_table);
     if (mem == HB_HOST) {
         dev_free(dphi);
         dev_free(dpsi);

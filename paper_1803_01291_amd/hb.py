@@ -79,6 +79,7 @@ _SIGS = {
     "hb_time": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)],
     "hb_sync": [_P],
     "hb_diagnostics": [_P, ctypes.POINTER(hb_diag)],
+    "hb_bubbles": [_P, ctypes.c_double, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
     "hb_set_tiling": [_P, _I, _I],
     "hb_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "hb_destroy": [_P],
@@ -91,6 +92,7 @@ _SIGS = {
     "hb_batch_read": [_P, _I, _P, _P, _I, _I],
     "hb_batch_sync": [_P],
     "hb_batch_set_tiling": [_P, _I, _I],
+    "hb_batch_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "hb_batch_destroy": [_P],
     "hb_pool_create": [ctypes.c_size_t, _I, _P, ctypes.POINTER(_P)],
     "hb_pool_admit": [_P, ctypes.POINTER(hb_config), _P, _P, _I, _I, _I64, ctypes.POINTER(_I)],
@@ -267,6 +269,14 @@ def hb_diagnostics(h: int, allow_nonfinite: bool = False) -> dict:
     return d.asdict()
 
 
+def hb_bubbles(h: int, eps: float = 0.0):
+    """(negative sets, positive sets): face-connected sets of {phi < -eps}
+    and {phi > eps} in the current state (the paper's bubbles, section 1)."""
+    neg, pos = _I64(), _I64()
+    _check(load().hb_bubbles(h, float(eps), ctypes.byref(neg), ctypes.byref(pos)))
+    return int(neg.value), int(pos.value)
+
+
 def hb_set_tiling(h: int, by: int, zc: int) -> None:
     _check(load().hb_set_tiling(h, int(by), int(zc)))
 
@@ -376,6 +386,14 @@ def hb_batch_sync(b: int) -> None:
 
 def hb_batch_set_tiling(b: int, by: int, zc: int) -> None:
     _check(load().hb_batch_set_tiling(b, int(by), int(zc)))
+
+
+def hb_batch_autotune(b: int, trial_steps: int = 5):
+    """Tune each precision group of the batch; returns ((by, zc) FP64,
+    (by, zc) FP32c), (-1, -1) for a precision the batch does not hold."""
+    by, zc = (_I * 2)(), (_I * 2)()
+    _check(load().hb_batch_autotune(b, int(trial_steps), by, zc))
+    return (by[0], zc[0]), (by[1], zc[1])
 
 
 def _forget(kind, handle):

@@ -9,8 +9,10 @@ arithmetic runs in libhb's kernels.
 
 Admission is FIFO with a bounded size-aware skip: when the head of the queue
 does not fit the unused budget, up to ``lookahead`` later requests that do fit
-may go first.  Latency of a request = completion (its state copied back to
-the host) - arrival.
+may go first.  The solves that finished in one advance are read back after
+the next advance has been enqueued, so their copies (on the pool's copy
+stream) overlap the device's work on the others.  Latency of a request =
+completion (its state copied back to the host) - arrival.
 """
 from __future__ import annotations
 
@@ -65,6 +67,21 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
     max_active = 0
     failed_slots = set()
     t0 = clock()
+    to_read: List[int] = []  # slots that finished in the previous advance
+
+    def collect(slot):
+        r, t_adm = inflight.pop(slot)
+        shape = r.phi0.shape
+        phi = np.empty(shape, np.float64)
+        psi = np.empty(shape, np.float64)
+        hb.hb_pool_read(pool, slot, phi, psi)
+        hb.hb_pool_release(pool, slot)
+        t_done = clock() - t0
+        done.append(Completion(r.index, r.arrival, t_adm, t_done,
+                               phi if keep_results else None, psi if keep_results else None,
+                               failed=slot in failed_slots))
+        failed_slots.discard(slot)
+
     try:
         while pending or queue or inflight:
             now = clock() - t0
@@ -82,31 +99,35 @@ def serve(requests: List[Request], budget_bytes: int, max_slots: int = 64, advan
                     continue
                 inflight[slot] = (r, clock() - t0)
                 del queue[i]
-            if not inflight:
+            active, _ = hb.hb_pool_stats(pool)
+            if active == 0 and not to_read:
+                if inflight:  # admitted with nothing to step: collect at once
+                    to_read = hb.hb_pool_poll(pool)
+                    for slot in to_read:
+                        collect(slot)
+                    to_read = []
+                    continue
                 if pending:  # idle: wait for the next arrival
                     time.sleep(max(0.0, pending[0].arrival - (clock() - t0)))
                     continue
                 if queue:
                     raise RuntimeError("a queued request can never fit the pool budget")
                 break
-            hb.hb_pool_advance(pool, advance_k)
-            advances += 1
-            if check_every and advances % check_every == 0:
-                failed_slots.update(hb.hb_pool_check(pool))
-            active, _ = hb.hb_pool_stats(pool)
+            if active:
+                hb.hb_pool_advance(pool, advance_k)
+                advances += 1
+                if check_every and advances % check_every == 0:
+                    failed_slots.update(hb.hb_pool_check(pool))
             max_active = max(max_active, active)
-            for slot in hb.hb_pool_poll(pool):
-                r, t_adm = inflight.pop(slot)
-                shape = r.phi0.shape
-                phi = np.empty(shape, np.float64)
-                psi = np.empty(shape, np.float64)
-                hb.hb_pool_read(pool, slot, phi, psi)
-                hb.hb_pool_release(pool, slot)
-                t_done = clock() - t0
-                done.append(Completion(r.index, r.arrival, t_adm, t_done,
-                                       phi if keep_results else None, psi if keep_results else None,
-                                       failed=slot in failed_slots))
-                failed_slots.discard(slot)
+            # results of the previous advance are copied out on the pool's copy
+            # stream while this advance runs
+            for slot in to_read:
+                collect(slot)
+            to_read = hb.hb_pool_poll(pool)
+            if not active:
+                for slot in to_read:
+                    collect(slot)
+                to_read = []
     finally:
         hb.hb_pool_destroy(pool)
     lat = np.array([c.latency for c in done]) if done else np.zeros(1)

@@ -254,3 +254,53 @@ def test_autotune_cache_file(hb, tmp_path, monkeypatch):
     assert second == (8, 7)
     assert len([l for l in cache.read_text().split("\n") if l]) == 1  # a hit appends nothing
     np.testing.assert_array_equal(phi1, phi2)
+
+
+def test_batch_autotune_bitwise_and_cache(hb, tmp_path, monkeypatch):
+    """hb_batch_autotune tunes each precision group of a batch, restores the
+    states bitwise (every solve still equals itself run alone), caches one
+    entry per group keyed by the members' grid mix, and a second batch of
+    the same mix takes the cached choices without appending; another mix
+    gets entries of its own."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HB_TUNE_CACHE", str(cache))
+    ws = mixed_workloads()
+    precs = [0, 1, 0, 1, 0]
+
+    def run(workloads):
+        cfgs = [hb.config_from_workload(w, p, hb.HB_USE_GRAPH) for w, p in zip(workloads, precs)]
+        b = hb.hb_batch_create(cfgs)
+        try:
+            for i, w in enumerate(workloads):
+                hb.hb_batch_set_initial(b, i, *w.initial())
+            hb.hb_batch_step(b, 3)
+            choice = hb.hb_batch_autotune(b, 1)
+            hb.hb_batch_step(b, 6)
+            outs = []
+            for i, w in enumerate(workloads):
+                p0, _ = w.initial()
+                phi, psi = np.empty_like(p0), np.empty_like(p0)
+                hb.hb_batch_read(b, i, phi, psi)
+                outs.append((phi, psi))
+        finally:
+            hb.hb_batch_destroy(b)
+        return choice, outs
+
+    def lines():
+        return [l for l in cache.read_text().split("\n") if l]
+
+    first, outs = run(ws)
+    assert all(by in (8, 11, 16) and zc >= 0 for by, zc in first)
+    assert len(lines()) == 2 and all("batch" in l for l in lines())
+    for (phi, psi), w, p in zip(outs, ws, precs):
+        ref = alone(hb, w, p, 9)
+        np.testing.assert_array_equal(phi, ref[0])
+        np.testing.assert_array_equal(psi, ref[1])
+    second, outs2 = run(ws)
+    assert second == first and len(lines()) == 2   # cache hits append nothing
+    for a, c in zip(outs, outs2):
+        np.testing.assert_array_equal(a[0], c[0])
+    other = list(ws)
+    other[0] = si.small_case(71, 21, 13, seed=21, steps=9)
+    run(other)
+    assert len(lines()) == 3   # the FP64 group's mix changed; the FP32c group's did not

@@ -203,3 +203,95 @@ def test_example7_parity(hb, oracle_mod):
     print(f"Example 7 (64^3 x 150): relative max-norm error {err:.3e}, negative nodes {d['negative']}")
     assert err <= 1e-12
     assert phi.min() < -0.01 * phi.max()   # the bubbles have formed
+
+
+def example2_workload(n, reading, steps=0):
+    """Section 3, Example 2 on the unit box (L = 5): mu^2 = 1, lambda = -1,
+    phi0 = 2 B, phi1 = 10 B, B of radius 0.2 at the centre; `reading` picks
+    the bump: "literal" = the printed exp(1/R^2 - 1/(R^2 - r^2)),
+    "scale_invariant" = exp(1 - 1/(1 - r^2/R^2)) (both equal 1 at the
+    centre; the literal one is much narrower)."""
+    nn, lo, hi = (n,) * 3, (0.0,) * 3, (1.0,) * 3
+    C = (0.5,) * 3
+    b = si.paper_bump(nn, lo, hi, C, 0.2) if reading == "literal" else si.cinf_bump(nn, lo, hi, 1.0, 0.2, C)
+    return si.Workload(f"example2_{reading}_{n}", nn, lo, hi, mu2=1.0, lam=-1.0, dt=1e-3, steps=steps,
+                       inv_L2=1.0 / 25.0, phi0=lambda: 2.0 * b, phi1=lambda: 10.0 * b)
+
+
+@pytest.mark.parametrize("reading", ["literal", "scale_invariant"])
+def test_example2_parity(hb, oracle_mod, reading):
+    """Example 2's data under both bump readings: GPU against the oracle at
+    48^3, dt = 1e-3, 300 steps (before any blow-up), every node."""
+    w = example2_workload(48, reading, 300)
+    (phi, psi, d), = run_segments(hb, w, [300])
+    err = oracle.rel_maxnorm(phi, psi, *oracle.solve_workload(w))
+    print(f"Example 2 ({reading}, 48^3 x 300): relative max-norm error {err:.3e}, max|phi| {d['linf_phi']:.3f}")
+    assert err <= 1e-12
+
+
+def test_example2_both_readings(hb):
+    """What each reading gives at 64^3 against the paper's account (max|phi|
+    about 2 up to t = 2, about 130 at t = 2.97, the integral of phi blowing
+    up shortly after; neither reading reproduces it):
+    * scale-invariant bump: max|phi| passes 100 by t = 0.7 and the state
+      turns non-finite before t = 1, which hb_diagnostics reports as
+      HB_E_NONFINITE (overflow of the solution, not a device fault);
+    * literal bump: the narrow pulse disperses, max|phi| falls below 0.2 by
+      t = 1 and stays below 0.2 to t = 4, while the integral of phi grows
+      throughout (the zero state is unstable for lambda < 0)."""
+    w = example2_workload(64, "scale_invariant")
+    p0, p1 = w.initial()
+    h = hb.hb_create(hb.config_from_workload(w))
+    try:
+        hb.hb_set_initial(h, p0, p1)
+        hb.hb_step(h, 700)
+        d = hb.hb_diagnostics(h)
+        print(f"Example 2 scale-invariant: max|phi| {d['linf_phi']:.1f} at t = 0.7")
+        assert d["linf_phi"] > 100
+        hb.hb_step(h, 300)
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_diagnostics(h)
+        assert e.value.code == hb.HB_E_NONFINITE
+        assert hb.hb_diagnostics(h, allow_nonfinite=True)["nonfinite"] > 0
+    finally:
+        hb.hb_destroy(h)
+    w = example2_workload(64, "literal")
+    segs = [100] * 40  # t = 0.1 .. 4.0
+    series = [(k + 1) * 0.1 for k in range(40)]
+    states = run_segments(hb, w, segs)
+    lin = [d["linf_phi"] for _, _, d in states]
+    integ = [d["integral"] for _, _, d in states]
+    print("Example 2 literal: max|phi| at t = 0.5, 1, 2, 2.97, 4:",
+          [round(lin[int(round(t * 10)) - 1], 4) for t in (0.5, 1.0, 2.0, 3.0, 4.0)])
+    assert lin[0] > 1.0 and max(lin[9:]) < 0.2
+    assert all(b > a for a, b in zip(integ, integ[1:]))
+    assert len(series) == len(lin)
+
+
+def test_example2_pool_evicts_blowup(hb):
+    """The scale-invariant Example 2 solve and a healthy one (Example 3's
+    data) share a pool: hb_pool_check stops the first once its state turns
+    non-finite (before t = 1), and the second runs to its end bitwise as it
+    does alone."""
+    bad = example2_workload(48, "scale_invariant")
+    good = unit_box_case(48, 1.0, -5.0, 0.3, 9.0, 2.0, 1e-3)
+    pool = hb.hb_pool_create(1 << 32, 4)
+    try:
+        sb = hb.hb_pool_admit(pool, hb.config_from_workload(bad), *bad.initial(), 1000)
+        sg = hb.hb_pool_admit(pool, hb.config_from_workload(good), *good.initial(), 1000)
+        failed_at = None
+        for k in range(20):
+            hb.hb_pool_advance(pool, 50)
+            f = hb.hb_pool_check(pool)
+            if f:
+                assert f == [sb] and failed_at is None
+                failed_at = 50 * (k + 1)
+        print(f"Example 2 (scale-invariant) stopped by hb_pool_check after {failed_at} steps")
+        assert failed_at is not None and failed_at <= 1000
+        assert sorted(hb.hb_pool_poll(pool)) == sorted([sb, sg])
+        phi = np.empty(good.n[::-1])
+        hb.hb_pool_read(pool, sg, phi, None)
+        good.steps = 1000
+        np.testing.assert_array_equal(phi, hb.solve_host(good, 1000)[0])
+    finally:
+        hb.hb_pool_destroy(pool)

@@ -1,12 +1,14 @@
 """Batched GPU radial solver (section 2.2 form) against the radial oracle.
 
-Bar: FP64 state-vector relative max norm <= max(1e-12, 20 x floor), where
-floor is the same norm between the oracle and the oracle with its difference
-quotients summed in mirrored order (a legitimate reordering), measured here
-for the same case.  The radial discretisation amplifies rounding differences
-near r = 0: for Example 3 the floor grows from 3e-14 after 100 steps to
-2.4e-12 after 2200 steps, and the GPU difference tracks it.  Every solve of a
-batch is bitwise equal to the same solve alone.
+Bar: FP64 state-vector relative max norm <= 1e-12.  The kernel evaluates
+every node in the oracle's operation order (no contraction, difference
+quotients divided by dr^2 and 12 dr) with the same host FP64 c(t), so the
+two agree far below the bar although the radial discretisation amplifies
+rounding differences near r = 0: the oracle against itself with its
+difference quotients summed in mirrored order and multiplied by reciprocals
+(a legitimate reordering) differs by 3e-14 after 100 steps and 2.4e-12 after
+2200 steps of Example 3; that floor is printed beside each case.  Every
+solve of a batch is bitwise equal to the same solve alone.
 """
 import oracle.radial as radial_mod
 import numpy as np
@@ -90,9 +92,10 @@ def reordered_oracle(p0, p1, dr, mu2, lam, dt, steps, t0, invL2):
 
 
 def bar(p0, p1, ref, dr, mu2, lam, dt, steps, t0, invL2):
+    """(the FP64 bar, the oracle's own reordering floor for this case)"""
     alt = reordered_oracle(p0, p1, dr, mu2, lam, dt, steps, t0, invL2)
     floor = rel(alt[0], alt[1], *ref)
-    return max(1e-12, 20 * floor), floor
+    return 1e-12, floor
 
 
 def test_radial_long_run_within_noise_floor(hb):
@@ -106,7 +109,7 @@ def test_radial_long_run_within_noise_floor(hb):
     tol, floor = bar(b, -5.0 * b, ref, dr, mu2, lam, dt, steps, t0, invL2)
     err = rel(phi, psi, *ref)
     print(f"radial Example 3, 2200 steps: GPU err {err:.3e}, oracle noise floor {floor:.3e}")
-    assert err <= min(tol, 1e-10)
+    assert err <= tol
     assert phi.min() < -1e-3 * np.max(np.abs(phi))  # the bubble of Example 3 has formed
 
 
@@ -186,7 +189,7 @@ def test_radial_errors(hb):
 def test_radial_sweep_full_size_sampled(hb):
     """The benchmark's radial sweep (4096 solves x 1000 nodes x 2000 steps, one
     launch, device-resident state): three solves against the oracle, each
-    within max(1e-12, 20 x its noise floor)."""
+    within 1e-12."""
     import torch
     import synth_inputs as si
     count, m, steps, dr, dt, invL2 = 4096, 1000, 2000, 5e-4, 1e-4, 1 / 25
