@@ -28,10 +28,13 @@ Prints ONE JSON line.  Extra objects:
                    whole-step launch per step and precision over all of them,
                    FP64 and FP32c, tiles from the batch autotuner (default
                    tiles timed beside), vs the same solves run one by one;
-  served        -- a Poisson request stream (50/s, N in {48..384}^3, 200-2000
-                   steps, FP64/FP32c) through the continuous-batching pool:
-                   p50/p99 latency and solves/s (offered load is far above
-                   capacity, so latency is mostly queueing);
+  served        -- the first 300 arrivals of a Poisson request stream (50/s,
+                   N in {48..384}^3, 200-2000 steps, FP64/FP32c) through the
+                   continuous-batching pool: p50/p99 latency and solves/s
+                   (offered load is far above capacity, so latency is mostly
+                   queueing);
+  serve_sweep   -- 12-arrival traces at 0.5, 1, 2, 4 and 8 requests/s: the
+                   latency knee;
   shard         -- a 512 x 512 x 64 FP64 slab (one GPU's share of 512^3 over
                    eight), timed like the main leg;
   radial        -- the batched radial parameter sweep (4096 solves) against
@@ -431,6 +434,11 @@ def cpu_baseline(w, steps, steps_1t):
     return out
 
 
+def progress(leg):
+    """One line on stderr as each leg starts (the JSON line stays alone on stdout)."""
+    print(f"bench: {leg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,12 +453,13 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-count", type=int, default=32)
+    ap.add_argument("--serve-count", type=int, default=300,
+                    help="arrivals of the served leg's trace (the first N of the 50/s stream)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-sweep", type=str, default="",
-                    help="comma-separated arrival rates (req/s): also run a trace of "
-                         "--serve-sweep-count arrivals at each (latency knee)")
-    ap.add_argument("--serve-sweep-count", type=int, default=24)
+    ap.add_argument("--serve-sweep", type=str, default="0.5,1,2,4,8",
+                    help="comma-separated arrival rates (req/s): a trace of --serve-sweep-count "
+                         "arrivals at each (the latency knee); empty to skip")
+    ap.add_argument("--serve-sweep-count", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-radial", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
@@ -538,6 +547,7 @@ def main():
                           "f64_over_f32_time": 1.8},
     }
     if not args.no_forms:
+        progress("forms")
         e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
         k32 = sum(ms32)
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
@@ -547,6 +557,7 @@ def main():
                                  "contract_19pass_equiv_GBps":
                                      sum(STAGEWISE_BYTES[1]) * N / (k32 * 1e-3) / 1e9}}
     if not args.no_probe:
+        progress("hbm_probe")
         from paper_1803_01291_amd import hb
         gib = 1 << 30
         copy = hb.hb_probe_bandwidth(0, gib, 20)
@@ -556,10 +567,13 @@ def main():
         # the kernel's own bytes against the measured streaming ceiling
         out["roofline"]["frac_of_copy"] = achieved / copy
     if not args.no_batch:
+        progress("batched")
         out["batched"] = run_batch(args.batch_count, args.batch_steps, 16)
     if not args.no_serve:
+        progress("served")
         out["served"] = run_serve(args.serve_count, args.serve_rate, 192.0)
     if args.serve_sweep:
+        progress("serve_sweep")
         out["serve_sweep"] = []
         for rate in (float(r) for r in args.serve_sweep.split(",")):
             out["serve_sweep"].append(run_serve(args.serve_sweep_count, rate, 192.0))
@@ -569,17 +583,23 @@ def main():
                   file=sys.stderr, flush=True)
     out["system"] = system_info()
     if not args.no_accuracy and args.n == 256:
+        progress("accuracy")
         out["accuracy"] = run_accuracy(w)
     if not args.no_shard:
+        progress("shard")
         out["shard"] = run_shard(200, 10)
     if not args.no_c3:
+        progress("precision_c3")
         out["precision_c3"] = run_precision_c3(args.c3_steps)
     if not args.no_paper_grid:
+        progress("paper_grid")
         out["paper_grid"] = run_paper_grid(200, 10)
     if not args.no_radial:
+        progress("radial")
         out["radial"] = run_radial(args.radial_count, 1000, args.radial_steps,
                                    0 if args.no_cpu else 4)
     if not args.no_cpu:
+        progress("cpu_baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(out), flush=True)
 

@@ -19,7 +19,8 @@
 // c(t) comes from a host FP64 table (c at t_n, t_n + dt/2 and t_n + dt for
 // each step of the launch), the values the 3-D path and the oracles use, and
 // the per-node arithmetic follows the plain definition's operation order
-// (difference quotients divided by dr^2 and 12 dr, no contraction).
+// (difference quotients divided by dr^2 and 12 dr with correctly rounded
+// quotients, no contraction).
 #include <hip/hip_runtime.h>
 
 #include "hb_internal.h"
@@ -35,6 +36,17 @@ constexpr int RAD_THREADS = 256;
 
 template <typename T>
 using gptr = __attribute__((address_space(1))) T*;
+
+// x / d, correctly rounded, from the correctly rounded reciprocal r = 1/d:
+// y = x r is within an ulp of the quotient, the remainder x - d y is exact
+// in one fused multiply-add, and y + r (x - d y) rounds to the quotient
+// (Markstein's final correction step for division with fused multiply-add;
+// valid away from overflow and underflow).  Two multiply-adds and a
+// multiply per quotient instead of a full division sequence.
+__device__ __forceinline__ double quot(double x, double d, double r) {
+    const double y = x * r;
+    return __builtin_fma(__builtin_fma(-d, y, x), r, y);
+}
 
 template <int NPT>
 __global__ void __launch_bounds__(RAD_THREADS)
@@ -64,6 +76,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
     const double dr = d.dr, mu2 = d.mu2, lam = d.lambda, dt = d.dt;
     const double hdt = dt / 2.0, dt6 = dt / 6.0;
     const double dr2 = dr * dr, dr12 = 12.0 * dr;
+    const double rdr2 = 1.0 / dr2, rdr12 = 1.0 / dr12;  // correctly rounded reciprocals
 
     // 2/r at the owned nodes, divided once (kept in registers up to 8 nodes
     // per thread; recomputed, with the same result, beyond)
@@ -77,10 +90,10 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
     // radial operator at node i (the thread's k-th) from S (ghosts filled)
     auto op = [&](const double* S, int i, int k) {
         const double um2 = S[i - 2], um1 = S[i - 1], u0 = S[i], up1 = S[i + 1], up2 = S[i + 2];
-        const double urr = (-1.0 / 12.0 * um2 + 4.0 / 3.0 * um1 - 5.0 / 2.0 * u0 + 4.0 / 3.0 * up1
-                            - 1.0 / 12.0 * up2) / dr2;
+        const double urr = quot(-1.0 / 12.0 * um2 + 4.0 / 3.0 * um1 - 5.0 / 2.0 * u0 + 4.0 / 3.0 * up1
+                                - 1.0 / 12.0 * up2, dr2, rdr2);
         if (i == 0) return 3.0 * urr;
-        const double ur = (um2 - 8.0 * um1 + 8.0 * up1 - up2) / dr12;
+        const double ur = quot(um2 - 8.0 * um1 + 8.0 * up1 - up2, dr12, rdr12);
         const double tr = KEEP_2R ? two_r[KEEP_2R ? k : 0] : 2.0 / ((double)i * dr);
         return tr * ur + urr;
     };
