@@ -325,6 +325,24 @@ typedef struct hb_radial_config {
 int hb_radial_solve(int count, const hb_radial_config* cfgs, double* phi, double* psi, int mem,
                     void* stream);
 
+/* hb_radial_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same solves with bitwise the same results, but phi and
+ * psi must be device memory (nodes back to back as for hb_radial_solve,
+ * read as the initial state and overwritten with the final one) and the call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * Descriptors and c(t) tables go into a fixed 8 MiB device scratch array
+ * that each device holds for the life of the process: a batch whose 80-byte
+ * descriptors (count x 80, rounded up to 256 bytes) leave no room for one
+ * step's table of 24 bytes per distinct (t0, dt, inv_L2) is rejected with
+ * HB_E_ARG before anything runs; launches then cover as many steps as the
+ * table room allows.  Every call on a device shares that device's scratch
+ * and rewrites it before use, so calls that overlap on one device (from
+ * several threads or streams) race and must be serialised.  Validation and
+ * stability errors as for hb_radial_solve.  Waits for completion. */
+int hb_radial_solve_noalloc(int count, const hb_radial_config* cfgs, double* phi, double* psi,
+                            void* stream);
+
 /* ---- measurement ----------------------------------------------------------- */
 
 /* Streamed-bandwidth probe on the current device (the achievable HBM streaming

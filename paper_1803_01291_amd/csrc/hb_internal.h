@@ -123,6 +123,11 @@ struct RadialDesc {
     double dr, mu2, lambda, inv_L2, t0, dt;
 };
 size_t radial_lds_bytes(int max_m);
+// Device scratch of the entry point that allocates nothing (descriptors and
+// c(t) table): its size, and its address on the current device (looked up
+// once per device; 0, or a HIP error code on failure).
+constexpr size_t RADIAL_SCRATCH_BYTES = (size_t)8 << 20;
+int radial_scratch(void** ptr);
 // steps n0 <= n < min(n1, steps) of every solve (state read from and
 // written back to phi, psi); ctab holds each solve's c(t) rows for those steps
 int launch_radial(const RadialDesc* descs, const double* ctab, int count, int max_m, double* phi,

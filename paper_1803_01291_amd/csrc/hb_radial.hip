@@ -23,6 +23,9 @@
 // quotients, no contraction).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "hb_internal.h"
 
 // every expression of this file is evaluated as written (no fused
@@ -199,6 +202,32 @@ hipError_t launch_radial_t(const RadialDesc* descs, const double* ctab, int coun
 }
 
 }  // namespace
+
+// Device scratch of the entry point that allocates nothing
+// (hb_radial_solve_noalloc): the descriptors and the c(t) table of its
+// launches.  Every device holds its own copy for the life of the process.
+// Host code never uses the array's name as a device address: the address on
+// the current device comes from hipGetSymbolAddress, looked up once per
+// device and kept.
+static __device__ __align__(256) unsigned char scratch[RADIAL_SCRATCH_BYTES];
+
+int radial_scratch(void** ptr) {
+    static std::mutex mu;
+    static std::vector<void*> addr;  // per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return 0;
+}
 
 size_t radial_lds_bytes(int max_m) { return (size_t)(2 * (max_m + 4)) * sizeof(double); }
 

@@ -2044,3 +2044,33 @@ extern "C" int hb_radial_solve(int count, const hb_radial_config* cfgs, double* 
     }
     return rc;
 }
+
+// The radial batch without device allocation: the same plan and launches as
+// hb_radial_solve, with descriptors and c(t) tables in the library's fixed
+// device scratch (its address on this device from radial_scratch).  The
+// state arrays are the caller's device memory.
+extern "C" int hb_radial_solve_noalloc(int count, const hb_radial_config* cfgs, double* phi, double* psi,
+                                       void* stream) {
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!cfgs || !phi || !psi)))
+        return fail(HB_E_ARG, "bad radial batch arguments");
+    if (count == 0) return HB_OK;
+    RadialPlan plan;
+    HB_TRY(radial_plan(count, cfgs, plan));
+    // descriptors first (256-byte aligned), then the c(t) table in the rest
+    const size_t desc_bytes = (size_t)round_up((long long)(plan.descs.size() * sizeof(RadialDesc)), 256);
+    if (desc_bytes >= RADIAL_SCRATCH_BYTES)
+        return fail(HB_E_ARG, "radial batch of %d solves: descriptors exceed the %zu-byte scratch", count,
+                    RADIAL_SCRATCH_BYTES);
+    const long long chunk =
+        radial_chunk(plan, (long long)((RADIAL_SCRATCH_BYTES - desc_bytes) / sizeof(double)));
+    if (chunk < 1)
+        return fail(HB_E_ARG, "radial batch: %zu distinct (t0, dt, inv_L2) exceed the %zu-byte scratch",
+                    plan.keys.size(), RADIAL_SCRATCH_BYTES);
+    void* base = nullptr;
+    HB_TRY(from_hip(radial_scratch(&base), "scratch address"));
+    RadialDesc* d_desc = (RadialDesc*)base;
+    double* d_table = (double*)((char*)base + desc_bytes);
+    return radial_run(plan, std::min(chunk, std::max<long long>(plan.max_steps, 1)), d_desc, d_table, phi,
+                      psi, (hipStream_t)stream);
+}

@@ -105,6 +105,7 @@ _SIGS = {
     "hb_pool_destroy": [_P],
     "hb_probe_bandwidth": [_I, ctypes.c_size_t, _I, ctypes.POINTER(ctypes.c_double)],
     "hb_radial_solve": [_I, ctypes.POINTER(hb_radial_config), _P, _P, _I, _P],
+    "hb_radial_solve_noalloc": [_I, ctypes.POINTER(hb_radial_config), _P, _P, _P],
 }
 
 
@@ -530,3 +531,22 @@ def hb_radial_solve(cfgs, phi, psi, stream=None) -> None:
     if d0 != HB_DTYPE_F64 or d1 != HB_DTYPE_F64 or m0 != m1:
         raise TypeError("phi and psi must be FP64 and in the same memory")
     _check(load().hb_radial_solve(len(cfgs), arr, p0, p1, m0, stream))
+
+
+def hb_radial_solve_noalloc(cfgs, phi, psi, stream=None) -> None:
+    """hb_radial_solve without device allocation: phi/psi must be FP64 torch
+    device tensors holding the solves back to back; the library keeps the
+    descriptors and c(t) tables in its fixed device scratch."""
+    arr = (hb_radial_config * len(cfgs))(*cfgs)
+    total = sum(int(c.m) for c in cfgs)
+    for x in (phi, psi):
+        if isinstance(x, np.ndarray) or x is None:
+            raise TypeError("hb_radial_solve_noalloc: phi and psi must be device tensors")
+        if x.numel() != total:
+            raise ValueError(f"hb_radial_solve_noalloc: array has {x.numel()} values, the solves have "
+                             f"{total} nodes")
+    p0, m0, d0, _k0 = _arr(phi)
+    p1, m1, d1, _k1 = _arr(psi)
+    if d0 != HB_DTYPE_F64 or d1 != HB_DTYPE_F64 or m0 != HB_DEVICE or m1 != HB_DEVICE:
+        raise TypeError("hb_radial_solve_noalloc: phi and psi must be FP64 device tensors")
+    _check(load().hb_radial_solve_noalloc(len(cfgs), arr, p0, p1, stream))
