@@ -43,11 +43,14 @@ using gptr = __attribute__((address_space(1))) T*;
 // x / d, correctly rounded, from the correctly rounded reciprocal r = 1/d:
 // y = x r is within an ulp of the quotient, the remainder x - d y is exact
 // in one fused multiply-add, and y + r (x - d y) rounds to the quotient
-// (Markstein's final correction step for division with fused multiply-add;
-// valid away from overflow and underflow).  Two multiply-adds and a
-// multiply per quotient instead of a full division sequence.
+// (Markstein's final correction step for division with fused multiply-add).
+// Two multiply-adds and a multiply per quotient instead of a full division
+// sequence.  The step needs an exact remainder, which quotients near the
+// subnormal range (|y| < 2^-960, far below any value that matters here)
+// may not have: those take the division itself.
 __device__ __forceinline__ double quot(double x, double d, double r) {
     const double y = x * r;
+    if (__builtin_fabs(y) < 0x1p-960) return x / d;
     return __builtin_fma(__builtin_fma(-d, y, x), r, y);
 }
 

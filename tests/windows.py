@@ -30,3 +30,19 @@ def sample_nodes(ny, nx, seed=11, count=6):
     rng = np.random.default_rng(seed)
     pts += [(int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(count)]
     return pts
+
+
+def window_solve3(oracle, phi0, phi1, z, y, x, w, steps, R=None):
+    """As window_solve, on a window in all three axes around node (z, y, x)
+    of a 3-D grid with initial data (phi0, phi1).  Returns the node's
+    (phi, psi) and the window's largest |phi|, |psi| after the steps."""
+    R = 4 * steps + 8 if R is None else R
+    nz, ny, nx = phi0.shape
+    z0, z1 = max(0, z - R), min(nz, z + R + 1)
+    y0, y1 = max(0, y - R), min(ny, y + R + 1)
+    x0, x1 = max(0, x - R), min(nx, x + R + 1)
+    p0 = np.ascontiguousarray(phi0[z0:z1, y0:y1, x0:x1])
+    p1 = np.ascontiguousarray(phi1[z0:z1, y0:y1, x0:x1])
+    p, s = oracle.solve(p0, p1, w.h, w.mu2, w.lam, w.dt, steps, t0=w.t0, inv_L2=w.inv_L2)
+    return (p[z - z0, y - y0, x - x0], s[z - z0, y - y0, x - x0],
+            max(float(np.max(np.abs(p))), float(np.max(np.abs(s)))))
