@@ -84,7 +84,7 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "b7dc7c48cf3fbddf"
+TRAFFIC_SOURCE_SHA = "bb1cfc814e2cdece"
 TRAFFIC_KERNEL = "step_kernel<double, false, 68, 15, false>"  # the 256^3 default region shape
 TRAFFIC_BYTES_F64 = 611.1 * 2 ** 20
 

@@ -25,7 +25,11 @@ def test_traffic_constant_matches_the_committed_profile():
     prof = open(os.path.join(ROOT, "profiles", "step_kernel_cube256.md")).read()
     sha = re.search(r"bench\.source_sha\(\)\): `([0-9a-f]+)`", prof).group(1)
     assert sha == bench.TRAFFIC_SOURCE_SHA
-    # the traffic table's row: raw fetch, scaled fetch, write, total (MiB)
+    # the traffic table's row: dispatches, raw fetch, scaled fetch, write, total (MiB)
     row = re.search(r"^\| `" + re.escape(bench.TRAFFIC_KERNEL) +
-                    r"` \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|$", prof, flags=re.M)
-    assert abs(float(row.group(4)) * 2 ** 20 - bench.TRAFFIC_BYTES_F64) < 0.05 * 2 ** 20
+                    r"` \| ([0-9]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \| ([0-9.]+) \|$", prof,
+                    flags=re.M)
+    assert row is not None
+    fetch_raw, fetch, write, total = (float(row.group(k)) for k in (2, 3, 4, 5))
+    assert abs(fetch - 2.0 * fetch_raw) < 0.15 and abs(total - fetch - write) < 0.15
+    assert abs(total * 2 ** 20 - bench.TRAFFIC_BYTES_F64) < 0.05 * 2 ** 20
