@@ -273,6 +273,11 @@ def run_precision_c3(steps):
                 out[name]["vs_oracle_sampled_rel_max"] = max((vp - gp).abs().max().item(),
                                                              (vq - gs).abs().max().item()) / gden
             out["oracle_nodes"] = len(g["points_zyx"])
+            # the oracle's own run of this workload (the one that stored the
+            # samples), timed by tests/golden/make_golden.py on its host
+            if "oracle_seconds" in g:
+                out["oracle_run"] = {"seconds": g["oracle_seconds"], "threads": g.get("oracle_threads"),
+                                     "pt_updates_per_s": w.points * steps / g["oracle_seconds"]}
     return out
 
 

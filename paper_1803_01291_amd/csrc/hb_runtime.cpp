@@ -1396,10 +1396,12 @@ struct hb_pool {
         hipEvent_t ready = nullptr;    // admission transfer complete (copy stream)
         hipEvent_t fin = nullptr;      // compute-stream point after its last step
     };
-    // a released solve, kept for an admission of the same footprint
+    // a released solve, kept for an admission whose fields and coefficient
+    // table need exactly its allocations
     struct Spare {
         std::unique_ptr<Solve> s;
-        size_t bytes = 0;
+        size_t bytes = 0;              // its footprint (counted against the budget)
+        size_t mem_bytes = 0;          // its field allocation
         hipEvent_t retired = nullptr;  // compute-stream point after which nothing touches it
     };
     std::vector<Slot> slots;
@@ -1545,11 +1547,14 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
             break;
         }
     if (free_slot < 0) return fail(HB_E_BUSY, "no free slot");
-    // a released solve of the same footprint is taken over (its allocation
-    // and coefficient table fit this configuration exactly)
+    // a released solve whose field allocation and coefficient table have
+    // exactly the sizes this configuration needs is taken over
+    const Layout need_L = plan_layout(*cfg, SCHEME_STEP);
+    const size_t need_mem = field_bytes(need_L) * (size_t)need_L.nfields;
+    const long long need_cap = ctab_capacity(steps + 1, 0);
     int reuse = -1;
     for (size_t i = 0; i < p->spares.size(); ++i)
-        if (p->spares[i].bytes == need) {
+        if (p->spares[i].mem_bytes == need_mem && p->spares[i].s->ctab_steps == need_cap) {
             reuse = (int)i;
             break;
         }
@@ -1569,7 +1574,7 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
             p->spares.erase(p->spares.begin() + (long)k);
         }
     }
-    if (p->in_use + (p->spare_bytes - (reuse >= 0 ? need : 0)) + need > p->budget)
+    if (p->in_use + (p->spare_bytes - (reuse >= 0 ? p->spares[reuse].bytes : 0)) + need > p->budget)
         return fail(HB_E_BUSY, "HBM budget exhausted");
     std::unique_ptr<Solve> s;
     if (reuse >= 0) {
@@ -1585,12 +1590,11 @@ int hb_pool_admit(hb_pool* p, const hb_config* cfg, const void* phi0, const void
         solve_views(*s, *cfg, SCHEME_STEP);
     } else {
         s = std::make_unique<Solve>();
-        const Layout L = plan_layout(*cfg, SCHEME_STEP);
-        HB_TRY(dev_alloc((void**)&s->mem, field_bytes(L) * (size_t)L.nfields, "solve state", p->xfer));
+        HB_TRY(dev_alloc((void**)&s->mem, need_mem, "solve state", p->xfer));
         solve_views(*s, *cfg, SCHEME_STEP);
-        const long long cap = ctab_capacity(steps + 1, 0);
-        HB_TRY(dev_alloc((void**)&s->ctab, (size_t)cap * 4 * sizeof(double), "coefficient table", p->xfer));
-        s->ctab_steps = cap;
+        HB_TRY(dev_alloc((void**)&s->ctab, (size_t)need_cap * 4 * sizeof(double), "coefficient table",
+                         p->xfer));
+        s->ctab_steps = need_cap;
     }
     if (mem == HB_DEVICE) {
         // device inputs are read in the pool stream's order
@@ -1814,6 +1818,7 @@ int hb_pool_release(hb_pool* p, int slot) {
     HIP_TRY(hipEventRecord(sp.retired, p->stream));
     // a join that never happened still orders the compute stream after the
     // admission copies (they precede every later copy-stream use anyway)
+    sp.mem_bytes = field_bytes(sl.s->L) * (size_t)sl.s->L.nfields;
     sp.s = std::move(sl.s);
     sp.bytes = sl.bytes;
     p->in_use -= sl.bytes;

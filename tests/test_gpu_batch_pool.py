@@ -304,3 +304,44 @@ def test_batch_autotune_bitwise_and_cache(hb, tmp_path, monkeypatch):
     other[0] = si.small_case(71, 21, 13, seed=21, steps=9)
     run(other)
     assert len(lines()) == 3   # the FP64 group's mix changed; the FP32c group's did not
+
+
+def test_pool_reuses_released_allocations_bitwise(hb):
+    """Released solves keep their device allocations for later admissions
+    whose fields and coefficient tables have the same sizes (here the same
+    grids with other data, coefficients, step counts and precision); the
+    later solves equal themselves run alone, bitwise, and the budget counts
+    the kept allocations."""
+    a = si.small_case(40, 24, 16, seed=51, steps=11)
+    b = si.small_case(33, 40, 17, seed=52, steps=7, mu2=0.7, lam=3.0)
+    a2 = si.small_case(40, 24, 16, seed=53, steps=19, mu2=1.3, lam=0.4, t0=0.1)
+    b2 = si.small_case(33, 40, 17, seed=54, steps=5, inv_L2=0.5)
+    pool = hb.hb_pool_create(1 << 30, 4)
+    try:
+        first = [hb.hb_pool_admit(pool, hb.config_from_workload(w, 0), *w.initial(), w.steps)
+                 for w in (a, b)]
+        for _ in range(3):
+            hb.hb_pool_advance(pool, 8)
+        assert sorted(hb.hb_pool_poll(pool)) == sorted(first)
+        _, used = hb.hb_pool_stats(pool)
+        for s in first:
+            hb.hb_pool_release(pool, s)
+        assert hb.hb_pool_stats(pool) == (0, 0)
+        precs = {id(a2): 1, id(b2): 0}
+        second = {}
+        for w in (b2, a2):
+            second[hb.hb_pool_admit(pool, hb.config_from_workload(w, precs[id(w)]), *w.initial(),
+                                    w.steps)] = w
+        assert hb.hb_pool_stats(pool)[1] == used   # the same footprints as the first two
+        for _ in range(4):
+            hb.hb_pool_advance(pool, 6)
+        assert sorted(hb.hb_pool_poll(pool)) == sorted(second)
+        for slot, w in second.items():
+            phi = np.empty(w.n[::-1])
+            psi = np.empty(w.n[::-1])
+            hb.hb_pool_read(pool, slot, phi, psi)
+            ref = alone(hb, w, precs[id(w)], w.steps)
+            np.testing.assert_array_equal(phi, ref[0])
+            np.testing.assert_array_equal(psi, ref[1])
+    finally:
+        hb.hb_pool_destroy(pool)
