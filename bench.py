@@ -38,7 +38,7 @@ Prints ONE JSON line.  Extra objects:
   shard         -- a 512 x 512 x 64 FP64 slab (one GPU's share of 512^3 over
                    eight), timed like the main leg;
   radial        -- the batched radial parameter sweep (4096 solves) against
-                   its LDS roofline;
+                   the FP64 vector peak (the kernel is bound by FP64 issue);
   paper_grid    -- the paper's longest run (section 3, Example 7) at its
                    default grid, 500^3 cells, dt = 1e-4, FP64 and FP32c: step
                    rate and the projected hours to t = 50 (5e5 steps) beside
@@ -299,11 +299,16 @@ def run_paper_grid(steps, warmup):
     return out
 
 
-# radial batch kernel: LDS bytes per node-step (per stage one write of the
-# stage input and five stencil reads, 8 B each; the state stays in registers)
-# and the LDS peak (128 B/clock/CU measured, 256 CUs, 2.4 GHz)
-RADIAL_LDS_BYTES = 4 * 6 * 8
-LDS_PEAK_GBS = 128 * 256 * 2.4
+# radial batch kernel: FP64 arithmetic per node-step of the kernel's main
+# loop (gfx950 code of radial_kernel<4>: 266 multiplies, 260 adds and 64
+# fused multiply-adds per thread and step for 4 nodes), as flops (a fused
+# multiply-add counts 2) and as instructions (each occupies a SIMD lane for
+# one of the issue slots behind the 78.6 TFLOP/s FP64 vector peak: 256 CUs x
+# 64 lanes x 2.4 GHz = 39.3e12 operations/s)
+RADIAL_FLOPS_PER_NODE_STEP = (266 + 260 + 2 * 64) / 4
+RADIAL_FP64_OPS_PER_NODE_STEP = (266 + 260 + 64) / 4
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP64_OPS_PEAK = 256 * 64 * 2.4e9
 
 
 def run_radial(count, m, steps, cpu_sample):
@@ -328,7 +333,7 @@ def run_radial(count, m, steps, cpu_sample):
     sec = time.perf_counter() - t0
     node_steps = count * m * steps
     rate = node_steps / sec
-    achieved = RADIAL_LDS_BYTES * rate / 1e9
+    achieved = RADIAL_FLOPS_PER_NODE_STEP * rate / 1e12
     cpu = None
     if cpu_sample > 0:
         from oracle.radial import radial_solve
@@ -343,9 +348,11 @@ def run_radial(count, m, steps, cpu_sample):
                "sample": f"{cpu_sample} of the solves, NumPy radial oracle, {cpu_sec:.1f} s"}
     return {"solves": count, "nodes": m, "steps": steps, "seconds": sec,
             "solves_per_s": count / sec, "node_updates_per_s": rate,
-            "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS,
-                         "bytes_per_node_step": RADIAL_LDS_BYTES},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                         "flops_per_node_step": RADIAL_FLOPS_PER_NODE_STEP,
+                         "fp64_ops_per_node_step": RADIAL_FP64_OPS_PER_NODE_STEP,
+                         "issue_frac": RADIAL_FP64_OPS_PER_NODE_STEP * rate / FP64_OPS_PEAK},
             "cpu_baseline": cpu}
 
 
