@@ -84,9 +84,9 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime sources they were measured on (the runtime picks the
 # tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "bb1cfc814e2cdece"
-TRAFFIC_KERNEL = "step_kernel<double, false, 68, 15, false>"  # the 256^3 default region shape
-TRAFFIC_BYTES_F64 = 611.1 * 2 ** 20
+TRAFFIC_SOURCE_SHA = "3e0cdda844a49923"
+TRAFFIC_KERNEL = "step_kernel<double, false, 36, 20, false>"  # the 256^3 default region shape
+TRAFFIC_BYTES_F64 = 562.8 * 2 ** 20
 
 
 def source_sha():
@@ -540,6 +540,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": frac, "traffic": traffic,
                      "traffic_over_alg": traffic / (own_b * N) if traffic else None,
+                     # the kernel and sources the traffic was measured on
+                     # (profiles/step_kernel_cube256.md); null traffic otherwise
+                     "traffic_kernel": TRAFFIC_KERNEL, "source_sha": source_sha(),
                      "kernel": {"step": "step_kernel (whole RK4 step)",
                                 "pairs": "pair_kernel x 2 (sum per step)",
                                 "stages": "stage_kernel x 4 (sum per step)"}[args.scheme],

@@ -193,10 +193,11 @@ int hb_bubbles(hb_solver* s, double eps, int64_t* negative_sets, int64_t* positi
  * blocks on the device); by in {8, 16}: rows of 64 columns per tile for the
  * stage-pair and per-stage kernels (default 16); for the whole-step kernel
  * by = 8 selects 32 x 24 tiles (1008-thread blocks), by = 16 selects 60 x 12
- * tiles (1024-thread blocks) and by = 11 selects 64 x 11 tiles (1020-thread
- * blocks; whole-step only, else HB_E_ARG).  The whole-step default is 60 x 12,
- * or 64 x 11 where the library's model of block rounds gives it at least 5%
- * less work (e.g. 256^3 and 512^3 grids).  Results do not depend on it. */
+ * tiles (1024-thread blocks), by = 11 selects 64 x 11 tiles (1020-thread
+ * blocks) and by = 20 selects 32 x 16 tiles (720-thread blocks); 11 and 20
+ * are whole-step only, else HB_E_ARG.  The whole-step default comes from the
+ * library's model of block rounds (e.g. 32 x 16 on a 256^3 grid, 64 x 11 on
+ * 512^3, 32 x 24 on 384^3).  Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 
 /* Time every candidate tile shape for `trial_steps` steps on the current

@@ -62,14 +62,17 @@ int launch_pair(int prec, int pair, int by, const SolveDesc* descs, const Tile* 
 // Whole-step kernel: one launch per RK4 step, on paired-state solves (cs = 2).
 // A block's threads own an rx x ry region: its interior tile of
 // (rx - 4) x (ry - 4) columns plus a 2-cell ring.  Shapes (`shape` indexes
-// this table), all 16 waves per CU: 36 x 28 (1008 threads; tiles 32 columns
-// wide), 64 x 16 (1024 threads; a region row is one wave) and 68 x 15 (1020
+// this table), one block per CU: 36 x 28 (1008 threads; tiles 32 columns
+// wide), 64 x 16 (1024 threads; a region row is one wave), 68 x 15 (1020
 // threads; tiles 64 columns wide, which cover multiples of 64 exactly and
-// start on 128-byte lines).  Bitwise equal to the stage-pair kernels.
+// start on 128-byte lines) and 36 x 20 (720 threads, three waves per SIMD;
+// 32 x 16 tiles, which cover a 256 x 256 plane in 128 tiles, so two z-chunks
+// of a 256^3 grid fill one round of 256 CUs).  Bitwise equal to the
+// stage-pair kernels.
 struct StepShape {
     int rx, ry, blocks_per_cu;
 };
-constexpr StepShape STEP_SHAPES[3] = {{36, 28, 1}, {64, 16, 1}, {68, 15, 1}};
+constexpr StepShape STEP_SHAPES[4] = {{36, 28, 1}, {64, 16, 1}, {68, 15, 1}, {36, 20, 1}};
 // periodic: some solve of the launch has periodic boundaries (selects the
 // kernel that reads each descriptor's boundary; else the zero-halo kernel)
 int launch_step(int prec, int shape, const SolveDesc* descs, const Tile* tiles, int ntiles,

@@ -602,12 +602,13 @@ pair_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
 // modulo 6 and the loop is unrolled by 6, so queue shifts are register
 // renaming rather than moves.
 //
-// Every shape runs 4 waves per SIMD (the second launch-bounds argument is the
-// minimum waves per SIMD, which caps registers at 128): 16-wave blocks, one
-// per CU.  PBC: the launch may hold periodic solves (each follows its own
-// descriptor); without it the kernel is the zero-halo one alone.
+// One block per CU (its LDS planes take most of the CU's 160 KB): the second
+// launch-bounds argument, the block's waves per SIMD, is 4 for the 16-wave
+// shapes (128 registers) and 3 for the 720-thread 36 x 20 shape.  PBC: the
+// launch may hold periodic solves (each follows its own descriptor); without
+// it the kernel is the zero-halo one alone.
 template <typename T, bool COMP, int SK_RX, int SK_RY, bool PBC>
-__global__ void __launch_bounds__(SK_RX * SK_RY, 4)
+__global__ void __launch_bounds__(SK_RX * SK_RY, (SK_RX * SK_RY + 255) / 256)
 step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles, int ntiles,
             long long kstep) {
     constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
@@ -1050,10 +1051,12 @@ hipError_t launch_step_t(int shape, const SolveDesc* descs, const Tile* tiles, i
     static_assert(STEP_SHAPES[0].rx == 36 && STEP_SHAPES[0].ry == 28, "shape table");
     static_assert(STEP_SHAPES[1].rx == 64 && STEP_SHAPES[1].ry == 16, "shape table");
     static_assert(STEP_SHAPES[2].rx == 68 && STEP_SHAPES[2].ry == 15, "shape table");
+    static_assert(STEP_SHAPES[3].rx == 36 && STEP_SHAPES[3].ry == 20, "shape table");
     switch (shape) {
         case 0: return launch_step_shape<T, COMP, 36, 28>(descs, tiles, ntiles, kstep, pbc, s);
         case 1: return launch_step_shape<T, COMP, 64, 16>(descs, tiles, ntiles, kstep, pbc, s);
         case 2: return launch_step_shape<T, COMP, 68, 15>(descs, tiles, ntiles, kstep, pbc, s);
+        case 3: return launch_step_shape<T, COMP, 36, 20>(descs, tiles, ntiles, kstep, pbc, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -580,9 +580,12 @@ int device_cus() {
 
 // whole-step kernel region shape (STEP_SHAPES): by = 8 selects 36 x 28
 // regions (32 x 24 tiles), by = 16 selects 64 x 16 regions (60 x 12 tiles),
-// by = 11 selects 68 x 15 regions (64 x 11 tiles; whole-step scheme only).
-int step_shape(int by) { return by == 16 ? 1 : by == 11 ? 2 : 0; }
-bool valid_by(int by, int scheme) { return by == 8 || by == 16 || (by == 11 && scheme == SCHEME_STEP); }
+// by = 11 selects 68 x 15 regions (64 x 11 tiles) and by = 20 selects 36 x 20
+// regions (32 x 16 tiles); the last two are whole-step shapes only.
+int step_shape(int by) { return by == 16 ? 1 : by == 11 ? 2 : by == 20 ? 3 : 0; }
+bool valid_by(int by, int scheme) {
+    return by == 8 || by == 16 || ((by == 11 || by == 20) && scheme == SCHEME_STEP);
+}
 
 // z-march length for one solve.  Blocks run in rounds of (CUs x blocks per
 // CU); a march of zc planes costs about zc + 4 planes (warm-up) rounded up to
@@ -619,20 +622,33 @@ int default_zc_step(const Layout& L, int by, int nmembers) {
     return plan_zc_step(L, by).zc;
 }
 
-// Default region shape of a single solve: 64 x 16, or 68 x 15 where the march
-// model gives it at least 3% (FP64) / 5% (FP32c) fewer block-planes, or
-// 36 x 28 where the model gives that at least 8% (FP64) / 15% (FP32c) fewer
-// block-planes than the better of the other two.  The model overstates the differences (a block's
-// cost also depends on its shape), so the margins are set from measurements
-// on eight grids (192^3 to 512^3, a 512 x 512 x 64 slab; both precisions;
-// two devices): the rule picks the fastest shape or one within 2% of it in
-// 31 of the 32 cases (192^3 FP32c: 4%), e.g. 68 x 15 on 256^3 and 512^3,
-// 36 x 28 on 384^3 (FP64 -8% against 64 x 16).  Batches and pools keep
-// 64 x 16.
+// Default region shape of a single solve.  First 36 x 20, where its march
+// cost weighted by the work of one of its planes (stage-1+2 region plus
+// tile), times a measured per-work penalty of its three-waves-per-SIMD blocks
+// (1.16 FP64, 1.12 FP32c), is at least 2% below the weighted costs of
+// 68 x 15 and 36 x 28: on grids whose x-y tiles and z-chunks fill whole
+// rounds of the device in 32 x 16 tiles but not in the others, e.g. 96^3,
+// 160^3 and 256^3 (FP64 -9%, -1.5%, -5%; FP32c -8%, -4%, -9.5% against the
+// next best shape), and on none of 128^3, 192^3, 224^3, 288^3, 320^3,
+// 384^3, 512^3 (where it loses 3-11%).  Else 64 x 16, or 68 x 15 where the
+// march model gives it at least 3% (FP64) / 5% (FP32c) fewer block-planes,
+// or 36 x 28 where the model gives that at least 8% (FP64) / 15% (FP32c)
+// fewer block-planes than the better of the other two.  The model overstates
+// the differences (a block's cost also depends on its shape), so the margins
+// are set from measurements on eight grids (192^3 to 512^3, a 512 x 512 x 64
+// slab; both precisions; two devices): the rule picks the fastest shape or
+// one within 2% of it in 31 of the 32 cases (192^3 FP32c: 4%), e.g. 68 x 15
+// on 512^3, 36 x 28 on 384^3 (FP64 -8% against 64 x 16).  Batches and pools
+// keep 64 x 16.
 int default_step_by(const Layout& L, int precision) {
     const double c16 = plan_zc_step(L, 16).cost, c11 = plan_zc_step(L, 11).cost;
-    const double c8 = plan_zc_step(L, 8).cost;
+    const double c8 = plan_zc_step(L, 8).cost, c20 = plan_zc_step(L, 20).cost;
     const bool f32c = precision == HB_F32C;
+    auto work = [](int by, double cost) {
+        const StepShape sh = STEP_SHAPES[step_shape(by)];
+        return cost * (sh.rx * sh.ry + (sh.rx - 4) * (sh.ry - 4));
+    };
+    if (work(20, c20) * (f32c ? 1.12 : 1.16) <= 0.98 * std::min(work(11, c11), work(8, c8))) return 20;
     if (c8 <= (f32c ? 0.85 : 0.92) * std::min(c16, c11)) return 8;
     return c11 <= (f32c ? 0.95 : 0.97) * c16 ? 11 : 16;
 }
@@ -1041,7 +1057,7 @@ int hb_bubbles(hb_solver* h, double eps, int64_t* negative_sets, int64_t* positi
 
 int hb_set_tiling(hb_solver* h, int by, int zc) {
     if (!h) return fail(HB_E_ARG, "solver is NULL");
-    if (!valid_by(by, h->g.scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11, whole-step scheme)");
+    if (!valid_by(by, h->g.scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11 or 20, whole-step scheme)");
     if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
     h->g.by = by;
     h->g.zc = zc;
@@ -1192,7 +1208,7 @@ int group_autotune(Group& g, int trial_steps, hipStream_t stream, int* best_by, 
     int maxz = 0;
     for (Solve* s : g.members) maxz = std::max(maxz, s->L.nz);
     if (g.scheme == SCHEME_STEP) {
-        for (int by : {16, 11, 8})
+        for (int by : {16, 11, 8, 20})
             for (int zc : {0, 16, 32, 64, 128, 256})
                 if (zc <= maxz) cand.push_back({by, zc});
     } else {
@@ -1345,7 +1361,7 @@ int hb_batch_sync(hb_batch* b) {
 
 int hb_batch_set_tiling(hb_batch* b, int by, int zc) {
     if (!b) return fail(HB_E_ARG, "batch is NULL");
-    if (!valid_by(by, b->groups[0].scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11, whole-step scheme)");
+    if (!valid_by(by, b->groups[0].scheme)) return fail(HB_E_ARG, "by must be 8 or 16 (or 11 or 20, whole-step scheme)");
     if (zc < 0) return fail(HB_E_ARG, "zc must be >= 0");
     for (Group& g : b->groups) {
         g.by = by;

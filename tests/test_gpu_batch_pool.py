@@ -149,7 +149,7 @@ def test_autotune_restores_state_bitwise(hb):
         hb.hb_set_initial(h, p0, p1)
         hb.hb_step(h, 2)
         by, zc = hb.hb_autotune(h, 2)
-        assert by in (8, 11, 16) and zc >= 0
+        assert by in (8, 11, 16, 20) and zc >= 0
         assert hb.hb_time(h)[1] == 2
         hb.hb_step(h, 4)
         phi, psi = np.empty_like(p0), np.empty_like(p0)
@@ -290,7 +290,7 @@ def test_batch_autotune_bitwise_and_cache(hb, tmp_path, monkeypatch):
         return [l for l in cache.read_text().split("\n") if l]
 
     first, outs = run(ws)
-    assert all(by in (8, 11, 16) and zc >= 0 for by, zc in first)
+    assert all(by in (8, 11, 16, 20) and zc >= 0 for by, zc in first)
     assert len(lines()) == 2 and all("batch" in l for l in lines())
     for (phi, psi), w, p in zip(outs, ws, precs):
         ref = alone(hb, w, p, 9)

@@ -30,8 +30,9 @@ def test_config1_full(hb, oracle_mod):
     assert err <= TOL64
 
 
-# Whole-step kernel tiles (the default scheme): 32 x 24 (by 8) and 60 x 12
-# (by 16); tiling (by, zc), zc = 0 for the library's z-march length.
+# Whole-step kernel tiles (the default scheme): 32 x 24 (by 8), 60 x 12
+# (by 16), 64 x 11 (by 11) and 32 x 16 (by 20); tiling (by, zc), zc = 0 for
+# the library's z-march length.
 @pytest.mark.parametrize("shape,tiling", [
     ((70, 21, 13), None),          # 3 x-tiles (32 + 32 + 6), one ragged y-tile
     ((130, 17, 40), (8, 7)),       # 5 x-tiles (ragged 2), z-marches of 7 (ragged 5)
@@ -43,6 +44,8 @@ def test_config1_full(hb, oracle_mod):
     ((130, 25, 19), (11, 6)),      # 3 x 3 tiles of 64 x 11 (ragged 2, 3), z ragged 1
     ((64, 11, 7), (11, 0)),        # exactly one 64 x 11 tile
     ((256, 23, 12), (11, 5)),      # 4 whole 64-column tiles, y ragged 1
+    ((70, 37, 15), (20, 4)),       # 3 x 3 tiles of 32 x 16 (ragged 6, 5), z ragged 3
+    ((32, 16, 9), (20, 0)),        # exactly one 32 x 16 tile
 ])
 def test_ragged_shapes(hb, oracle_mod, shape, tiling):
     w = si.small_case(*shape, seed=sum(shape), steps=12)
@@ -128,8 +131,8 @@ def test_tiling_does_not_change_results(hb, flags):
     w = si.small_case(90, 30, 33, seed=9, steps=6)
     ref = run_gpu(hb, w, tiling=(8, 0), flags=flags)
     shapes = [(16, 0), (8, 5), (16, 11), (8, 1), (16, 2)]
-    if flags == 0:  # the 64 x 11 tiles of the whole-step kernel
-        shapes += [(11, 0), (11, 4), (11, 1)]
+    if flags == 0:  # the 64 x 11 and 32 x 16 tiles of the whole-step kernel
+        shapes += [(11, 0), (11, 4), (11, 1), (20, 0), (20, 5), (20, 1)]
     for t in shapes:
         got = run_gpu(hb, w, tiling=t, flags=flags)
         np.testing.assert_array_equal(ref[0], got[0])
@@ -245,12 +248,13 @@ def test_errors(hb):
             assert e.value.code == hb.HB_E_ARG
     finally:
         hb.hb_destroy(h)
-    # 64 x 11 tiles exist for the whole-step kernel only
+    # 64 x 11 and 32 x 16 tiles exist for the whole-step kernel only
     h = hb.hb_create(hb.config_from_workload(w, flags=hb.HB_PAIRWISE))
     try:
-        with pytest.raises(hb.HBError) as e:
-            hb.hb_set_tiling(h, 11, 0)
-        assert e.value.code == hb.HB_E_ARG
+        for by in (11, 20):
+            with pytest.raises(hb.HBError) as e:
+                hb.hb_set_tiling(h, by, 0)
+            assert e.value.code == hb.HB_E_ARG
     finally:
         hb.hb_destroy(h)
     bad = hb.config_from_workload(w)

@@ -45,6 +45,7 @@ def oracle_solve(w):
     ((70, 21, 13), None),        # ragged tiles in x and y
     ((130, 25, 19), (11, 6)),    # 64 x 11 tiles, z-marches of 6
     ((64, 16, 9), (16, 4)),      # 60 x 12 tiles
+    ((40, 35, 10), (20, 3)),     # 32 x 16 tiles, ragged in x and y
     ((5, 3, 7), None),           # axes shorter than the reach of one step
     ((1, 2, 6), (8, 0)),         # one- and two-cell axes: every neighbour wraps onto itself
     ((33, 1, 1), None),
