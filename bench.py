@@ -82,18 +82,26 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs (profiles/
 # step_kernel_cube256.md), each scaled by the counter's reading for the plain
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
-# kernel and runtime sources they were measured on (the runtime picks the
-# tiling); any other source reports null.
-TRAFFIC_SOURCE_SHA = "3e0cdda844a49923"
+# kernel and runtime code they were measured on (the runtime picks the
+# tiling; source_sha() below); any other code reports null.
+TRAFFIC_SOURCE_SHA = "47f11e7d1167ff6b"
 TRAFFIC_KERNEL = "step_kernel<double, false, 36, 20, false>"  # the 256^3 default region shape
 TRAFFIC_BYTES_F64 = 562.8 * 2 ** 20
 
 
 def source_sha():
+    """Hash of the code that decides the whole-step kernel's traffic: the
+    kernels and the runtime that tiles them, with comments and whitespace
+    taken out (a comment edit does not invalidate a measurement; any code
+    edit does)."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in ("hb_kernels.hip", "hb_runtime.cpp"):
-        h.update(open(os.path.join(ROOT, "paper_1803_01291_amd", "csrc", f), "rb").read())
+    for f in ("hb_kernels.hip", "hb_runtime.cpp", "hb_internal.h"):
+        text = open(os.path.join(ROOT, "paper_1803_01291_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

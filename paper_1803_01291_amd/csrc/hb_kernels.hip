@@ -614,7 +614,7 @@ step_kernel(const SolveDesc* __restrict__ descs, const Tile* __restrict__ tiles,
     constexpr int SK_QX = SK_RX + 4, SK_QY = SK_RY + 4;  // R4
     constexpr int SK_NOUTER = SK_QX * SK_QY - SK_RX * SK_RY;
     // LDS row pitch of the R4 planes.  Where a region row is not one wave
-    // (68 x 15, 36 x 28), one wave holds pieces of two or three rows; a pitch
+    // (68 x 15, 36 x 28, 36 x 20), one wave holds pieces of two or three rows; a pitch
     // of the region width plus 256 bytes keeps those pieces in the bank order
     // of one contiguous run (with the natural pitch 9% (68 x 15) and 16%
     // (36 x 28) of the LDS cycles were bank conflicts; 2-7% of the step)
