@@ -105,13 +105,18 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0):
+def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0, repeats=None):
+    """Time `steps` RK4 steps after `warmup`, then the per-kernel device time
+    of `timed_stage_steps` single-step launches.  With repeats = (r, k), r
+    further timed runs of k steps each follow the timed steps, and their ms
+    per step come back as a fourth element."""
     import numpy as np
     import torch
     from paper_1803_01291_amd import hb
 
     p0, p1 = w.initial()
     h = hb.hb_create(hb.config_from_workload(w, precision, flags))
+    rep_ms = []
     try:
         hb.hb_set_initial(h, p0, p1)
         hb.hb_step(h, warmup)
@@ -122,10 +127,19 @@ def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0):
         hb.hb_sync(h)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        if repeats:
+            r, k = repeats
+            for _ in range(r):
+                t1 = time.perf_counter()
+                hb.hb_step(h, k)
+                hb.hb_sync(h)
+                rep_ms.append((time.perf_counter() - t1) * 1e3 / k)
         stage_ms = hb.hb_step_timed(h, timed_stage_steps)
         d = hb.hb_diagnostics(h, allow_nonfinite=True)
     finally:
         hb.hb_destroy(h)
+    if repeats:
+        return elapsed, [m / timed_stage_steps for m in stage_ms], d, rep_ms
     return elapsed, [m / timed_stage_steps for m in stage_ms], d
 
 
@@ -493,6 +507,9 @@ def main():
     ap.add_argument("--scheme", choices=("step", "pairs", "stages"), default="step",
                     help="3-D scheme of the single-solve legs: the whole-step kernel (default) "
                          "or, for comparison, the stage-pair or per-stage kernels")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of the main leg after the timed steps (median and min reported)")
+    ap.add_argument("--repeat-steps", type=int, default=200)
     ap.add_argument("--radial-count", type=int, default=4096)
     ap.add_argument("--radial-steps", type=int, default=2000)
     ap.add_argument("--forms", action="store_true", help="(on by default)")
@@ -511,7 +528,8 @@ def main():
     N = w.points
     from paper_1803_01291_amd import hb as _hb
     flags = {"step": 0, "pairs": _hb.HB_PAIRWISE, "stages": _hb.HB_STAGEWISE}[args.scheme]
-    elapsed, stage_ms, diag = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps, flags)
+    elapsed, stage_ms, diag, rep_ms = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps, flags,
+                                              repeats=(args.repeats, args.repeat_steps))
     # the whole-step kernel is one launch per step; the comparison schemes'
     # kernels are summed over the step
     kernel_ms = sum(stage_ms)
@@ -560,6 +578,11 @@ def main():
                      "contract_19pass_equiv_GBps": contract,
                      "step_frac": own_b * N / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS},
         "state_check": {"linf_phi": diag["linf_phi"], "nonfinite": diag["nonfinite"]},
+        # the same solve timed again in short runs after the timed region:
+        # the spread of ms per step on this device (not part of `value`)
+        "repeats": ({"runs": len(rep_ms), "steps_each": args.repeat_steps, "ms_per_step": rep_ms,
+                     "median_ms": sorted(rep_ms)[len(rep_ms) // 2], "min_ms": min(rep_ms)}
+                    if rep_ms else None),
         # the paper's only timing (section 2.1): 27 h to reach t = 50 on one
         # Tesla K40c, with the default grid and step of section 3 (500^3
         # points, dt 1e-4: 5e5 RK4 steps), i.e. about 6.4e8 point-updates/s;
