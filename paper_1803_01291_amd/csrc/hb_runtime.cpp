@@ -638,8 +638,10 @@ int default_zc_step(const Layout& L, int by, int nmembers) {
 // are set from measurements on eight grids (192^3 to 512^3, a 512 x 512 x 64
 // slab; both precisions; two devices): the rule picks the fastest shape or
 // one within 2% of it in 31 of the 32 cases (192^3 FP32c: 4%), e.g. 68 x 15
-// on 512^3, 36 x 28 on 384^3 (FP64 -8% against 64 x 16).  Batches and pools
-// keep 64 x 16.
+// on 512^3, 36 x 28 on 384^3 (FP64 -8% against 64 x 16).  A later sweep of
+// the whole rule over 14 cubes (96^3 to 512^3, both precisions) found its
+// pick the fastest shape or within 2.8% of it in all 28 cases.  Batches and
+// pools keep 64 x 16.
 int default_step_by(const Layout& L, int precision) {
     const double c16 = plan_zc_step(L, 16).cost, c11 = plan_zc_step(L, 11).cost;
     const double c8 = plan_zc_step(L, 8).cost, c20 = plan_zc_step(L, 20).cost;
