@@ -55,6 +55,34 @@ def test_batch_bitwise_equals_alone(hb, graph):
         np.testing.assert_array_equal(psi, ref[1])
 
 
+@pytest.mark.parametrize("tiling", [(20, 0), (20, 5), (11, 7), (8, 0)])
+def test_batch_tilings_bitwise_equal_alone(hb, tiling):
+    """Every whole-step region shape over a tile table of uneven solves
+    (32 x 16, 64 x 11 and 32 x 24 tiles; library and short z-marches) gives
+    each solve the bits it has alone with the single-solve default."""
+    ws = mixed_workloads()
+    precs = [1, 0, 1, 0, 1]
+    cfgs = [hb.config_from_workload(w, p) for w, p in zip(ws, precs)]
+    b = hb.hb_batch_create(cfgs)
+    try:
+        hb.hb_batch_set_tiling(b, *tiling)
+        for i, w in enumerate(ws):
+            hb.hb_batch_set_initial(b, i, *w.initial())
+        hb.hb_batch_step(b, 11)
+        outs = []
+        for i, w in enumerate(ws):
+            p0, _ = w.initial()
+            phi, psi = np.empty_like(p0), np.empty_like(p0)
+            hb.hb_batch_read(b, i, phi, psi)
+            outs.append((phi, psi))
+    finally:
+        hb.hb_batch_destroy(b)
+    for (phi, psi), w, p in zip(outs, ws, precs):
+        ref = alone(hb, w, p, 11)
+        np.testing.assert_array_equal(phi, ref[0])
+        np.testing.assert_array_equal(psi, ref[1])
+
+
 def test_batch_vs_oracle(hb, oracle_mod):
     ws = mixed_workloads()[:3]
     cfgs = [hb.config_from_workload(w) for w in ws]
