@@ -10,11 +10,13 @@
 //
 // One workgroup per solve; the workgroup runs all of its time steps in one
 // launch (solves are independent, so no grid synchronisation is needed).
-// Thread t owns nodes t, t + 256, ...: their Y_phi, Y_psi and G1..G3 stay in
-// registers.  Only the stage input S_phi, whose stencil spans other threads'
-// nodes, goes through LDS, in two buffers used by alternate stages, so each
-// stage needs one barrier.  The owners of nodes 1 and 2 also write the even
-// ghosts S[-1], S[-2].  Stage inputs are formed as in the 3-D kernels (G
+// Thread t owns a run of consecutive nodes (NPT t .. NPT t + NPT - 1): their
+// Y_phi, Y_psi and G1..G3 stay in registers.  Only the stage input S_phi
+// goes through LDS, in two buffers used by alternate stages, so each stage
+// needs one barrier; a node's stencil takes its run's own values from
+// registers and only the two values on each side of the run from LDS (4
+// reads per thread and stage instead of 5 per node).  The owners of nodes 1
+// and 2 also write the even ghosts S[-1], S[-2].  Stage inputs are formed as in the 3-D kernels (G
 // storage: only the psi component of each stage derivative is kept).
 // c(t) comes from a host FP64 table (c at t_n, t_n + dt/2 and t_n + dt for
 // each step of the launch), the values the 3-D path and the oracles use, and
@@ -55,6 +57,21 @@ __device__ __forceinline__ double quot(double x, double d, double r) {
     return __builtin_fma(__builtin_fma(-d, y, x), r, y);
 }
 
+// LDS layout of a stage input: node j lives in row j mod NPT, column
+// floor(j / NPT) + 2 of an NPT x (RAD_THREADS + 4) array, so thread t's run
+// of nodes NPT t .. NPT t + NPT - 1 is column t + 2, and a wave's threads
+// write and read consecutive doubles of one row (no bank conflicts).  The
+// two columns on each side hold the even ghosts S[-1] = S[1], S[-2] = S[2]
+// (column 1, and column 0 for NPT = 1) and nodes past the last thread's run,
+// which stay zero.
+constexpr int RAD_COLS = RAD_THREADS + 4;
+
+template <int NPT>
+__device__ __forceinline__ int rad_pos(int j) {
+    const int q = j >= 0 ? j / NPT : -((-j + NPT - 1) / NPT);  // floor(j / NPT)
+    return (j - q * NPT) * RAD_COLS + q + 2;
+}
+
 template <int NPT>
 __global__ void __launch_bounds__(RAD_THREADS)
 radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ ctab,
@@ -62,19 +79,19 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
     extern __shared__ double lds[];
     const RadialDesc d = descs[blockIdx.x];
     const int m = d.m;
-    // two stage-input buffers, each S[-2 .. m+1]: 2 ghost slots, the nodes,
-    // and 2 zeros at and beyond r = R
-    double* const Sb[2] = {lds + 2, lds + (m + 4) + 2};
-    if (threadIdx.x < 8) {
-        const int b = threadIdx.x >> 2, k = threadIdx.x & 3;
-        Sb[b][k < 2 ? k - 2 : m + k - 2] = 0.0;
-    }
+    // two stage-input buffers; zero first (the ghost columns are rewritten
+    // every stage, the columns past the last run stay zero: phi = 0 at and
+    // beyond r = R)
+    constexpr int BUF = NPT * RAD_COLS;
+    double* const Sb[2] = {lds, lds + BUF};
+    for (int k = threadIdx.x; k < 2 * BUF; k += RAD_THREADS) lds[k] = 0.0;
     gptr<double> gp = (gptr<double>)(phi + d.offset);
     gptr<double> gs = (gptr<double>)(psi + d.offset);
+    const int j0 = threadIdx.x * NPT;  // this thread's first node
     double yp[NPT], ys[NPT], g1[NPT], g2[NPT], g3[NPT], sv[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int i = threadIdx.x + k * RAD_THREADS;
+        const int i = j0 + k;
         yp[k] = i < m ? gp[i] : 0.0;
         ys[k] = i < m ? gs[i] : 0.0;
         g1[k] = g2[k] = g3[k] = sv[k] = 0.0;
@@ -91,12 +108,22 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
     double two_r[KEEP_2R ? NPT : 1];
 #pragma unroll
     for (int k = 0; k < (KEEP_2R ? NPT : 1); ++k) {
-        const int i = threadIdx.x + k * RAD_THREADS;
+        const int i = j0 + k;
         two_r[k] = i > 0 ? 2.0 / ((double)i * dr) : 0.0;
     }
+    // the stage input at node j0 + k + off: from this thread's registers
+    // inside its run, else from LDS (the neighbouring runs, the ghosts, the
+    // zeros); the same values either way, since the LDS copy is written from
+    // the registers
+    auto at = [&](const double* S, int k, int off) -> double {
+        const int kk = k + off;
+        if (kk >= 0 && kk < NPT) return sv[kk];
+        return S[rad_pos<NPT>(j0 + kk)];
+    };
     // radial operator at node i (the thread's k-th) from S (ghosts filled)
     auto op = [&](const double* S, int i, int k) {
-        const double um2 = S[i - 2], um1 = S[i - 1], u0 = S[i], up1 = S[i + 1], up2 = S[i + 2];
+        const double um2 = at(S, k, -2), um1 = at(S, k, -1), u0 = sv[k], up1 = at(S, k, 1),
+                     up2 = at(S, k, 2);
         const double urr = quot(-1.0 / 12.0 * um2 + 4.0 / 3.0 * um1 - 5.0 / 2.0 * u0 + 4.0 / 3.0 * up1
                                 - 1.0 / 12.0 * up2, dr2, rdr2);
         if (i == 0) return 3.0 * urr;
@@ -104,20 +131,20 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
         const double tr = KEEP_2R ? two_r[KEEP_2R ? k : 0] : 2.0 / ((double)i * dr);
         return tr * ur + urr;
     };
-    // publish this thread's stage inputs sv into S (and the mirrored ghosts)
+    // publish this thread's stage inputs sv into S (and the mirrored ghosts);
+    // nodes at and past m hold zeros in sv, so their slots keep S = 0 there
     auto put = [&](double* S) {
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = threadIdx.x + k * RAD_THREADS;
-            if (i < m) {
-                S[i] = sv[k];
-                if (i == 1 || i == 2) S[-i] = sv[k];
-            }
+            const int i = j0 + k;
+            S[rad_pos<NPT>(i)] = sv[k];
+            if (i == 1 || i == 2) S[rad_pos<NPT>(-i)] = sv[k];
         }
     };
 
     const long long nend = d.steps < n1 ? d.steps : n1;
     const gptr<const double> ct = (gptr<const double>)(ctab + d.ctab);
+    __syncthreads();  // the zeroed buffers
     for (long long n = n0; n < nend; ++n) {
         // c(t) at the stage times of step n (host FP64 table of this launch)
         const long long j = 3 * (n - n0);
@@ -129,7 +156,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = threadIdx.x + k * RAD_THREADS;
+            const int i = j0 + k;
             if (i < m) {
                 const double s = sv[k];
                 g1[k] = -3.0 * ys[k] + c1 * op(Sb[0], i, k) + mu2 * s - lam * s * s * s;
@@ -142,7 +169,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = threadIdx.x + k * RAD_THREADS;
+            const int i = j0 + k;
             if (i < m) {
                 const double s = sv[k];
                 g2[k] = -3.0 * (ys[k] + hdt * g1[k]) + c2 * op(Sb[1], i, k) + mu2 * s - lam * s * s * s;
@@ -155,7 +182,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = threadIdx.x + k * RAD_THREADS;
+            const int i = j0 + k;
             if (i < m) {
                 const double s = sv[k];
                 g3[k] = -3.0 * (ys[k] + hdt * g2[k]) + c2 * op(Sb[0], i, k) + mu2 * s - lam * s * s * s;
@@ -168,7 +195,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = threadIdx.x + k * RAD_THREADS;
+            const int i = j0 + k;
             if (i < m) {
                 const double s = sv[k];
                 const double y2 = ys[k], e1 = g1[k], e2 = g2[k], e3 = g3[k];
@@ -184,7 +211,7 @@ radial_kernel(const RadialDesc* __restrict__ descs, const double* __restrict__ c
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int i = threadIdx.x + k * RAD_THREADS;
+        const int i = j0 + k;
         if (i < m) {
             gp[i] = yp[k];
             gs[i] = ys[k];
@@ -233,20 +260,25 @@ int radial_scratch(void** ptr) {
     return 0;
 }
 
-size_t radial_lds_bytes(int max_m) { return (size_t)(2 * (max_m + 4)) * sizeof(double); }
+int radial_npt(int max_m) {
+    const int npt = (max_m + RAD_THREADS - 1) / RAD_THREADS;
+    return npt <= 1 ? 1 : npt <= 2 ? 2 : npt <= 4 ? 4 : npt <= 8 ? 8 : npt <= 11 ? 11 : 0;
+}
+
+size_t radial_lds_bytes(int max_m) { return (size_t)(2 * radial_npt(max_m) * RAD_COLS) * sizeof(double); }
 
 int launch_radial(const RadialDesc* descs, const double* ctab, int count, int max_m, double* phi,
                   double* psi, long long n0, long long n1, void* stream) {
     if (count <= 0) return 0;
     const size_t bytes = radial_lds_bytes(max_m);
     hipStream_t s = (hipStream_t)stream;
-    const int npt = (max_m + RAD_THREADS - 1) / RAD_THREADS;
+    const int npt = radial_npt(max_m);
     hipError_t e;
-    if (npt <= 1) e = launch_radial_t<1>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 2) e = launch_radial_t<2>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 4) e = launch_radial_t<4>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 8) e = launch_radial_t<8>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
-    else if (npt <= 11) e = launch_radial_t<11>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    if (npt == 1) e = launch_radial_t<1>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt == 2) e = launch_radial_t<2>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt == 4) e = launch_radial_t<4>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt == 8) e = launch_radial_t<8>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
+    else if (npt == 11) e = launch_radial_t<11>(descs, ctab, count, bytes, phi, psi, n0, n1, s);
     else return (int)hipErrorInvalidValue;
     return (int)e;
 }
