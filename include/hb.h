@@ -200,6 +200,13 @@ int hb_bubbles(hb_solver* s, double eps, int64_t* negative_sets, int64_t* positi
  * 512^3, 32 x 24 on 384^3).  Results do not depend on it. */
 int hb_set_tiling(hb_solver* s, int by, int zc);
 
+/* The tiling (by, zc as in hb_set_tiling) hb_create would give a single
+ * solve of cfg: the region shape and z-march length from the library's model
+ * of block rounds on the current device (256 CUs assumed when no device is
+ * visible, so it also answers on a host without a GPU; it launches nothing).
+ * HB_E_ARG / HB_E_CFL as hb_create for an invalid cfg; by, zc untouched then. */
+int hb_default_tiling(const hb_config* cfg, int* by, int* zc);
+
 /* Time every candidate tile shape for `trial_steps` steps on the current
  * state, keep the fastest, and restore the state (bitwise).  The choice is
  * cached per (device, precision, grid) in the text file named by the

@@ -872,6 +872,22 @@ int hb_set_allocator(hb_alloc_fn alloc, hb_free_fn release, void* ctx) {
     return HB_OK;
 }
 
+int hb_default_tiling(const hb_config* cfg, int* by, int* zc) {
+    g_last_error.clear();
+    if (!by || !zc) return fail(HB_E_ARG, "NULL argument");
+    HB_TRY(validate(cfg));
+    const int scheme = scheme_of(cfg->flags);
+    const Layout L = plan_layout(*cfg, scheme);
+    if (scheme == SCHEME_STEP) {
+        *by = default_step_by(L, cfg->precision);
+        *zc = default_zc_step(L, *by, 1);
+    } else {
+        *by = DEFAULT_BY;
+        *zc = default_zc(L, DEFAULT_BY);
+    }
+    return HB_OK;
+}
+
 size_t hb_footprint(const hb_config* cfg) {
     if (!cfg) return 0;
     hb_config c = *cfg;

@@ -81,6 +81,7 @@ _SIGS = {
     "hb_diagnostics": [_P, ctypes.POINTER(hb_diag)],
     "hb_bubbles": [_P, ctypes.c_double, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
     "hb_set_tiling": [_P, _I, _I],
+    "hb_default_tiling": [ctypes.POINTER(hb_config), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "hb_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "hb_destroy": [_P],
     "hb_footprint": [ctypes.POINTER(hb_config)],
@@ -292,6 +293,13 @@ def hb_destroy(h: int) -> None:
     if h:
         _GRIDS.pop(("s", h), None)
         _check(load().hb_destroy(h))
+
+
+def hb_default_tiling(cfg: hb_config):
+    """(by, zc) that hb_create would choose for a single solve of cfg."""
+    by, zc = _I(), _I()
+    _check(load().hb_default_tiling(ctypes.byref(cfg), ctypes.byref(by), ctypes.byref(zc)))
+    return by.value, zc.value
 
 
 def hb_footprint(cfg: hb_config) -> int:
