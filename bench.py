@@ -84,7 +84,7 @@ STAGEWISE_BYTES = {0: [24, 32, 40, 56], 1: [12, 16, 20, 44]}
 # copy probe of known size (FETCH x 2.0, WRITE x 1.0).  Valid only for the
 # kernel and runtime code they were measured on (the runtime picks the
 # tiling; source_sha() below); any other code reports null.
-TRAFFIC_SOURCE_SHA = "9fa8551b707f25ad"
+TRAFFIC_SOURCE_SHA = "23bf8311d98de432"
 TRAFFIC_KERNEL = "step_kernel<double, false, 36, 20, false>"  # the 256^3 default region shape
 TRAFFIC_BYTES_F64 = 562.8 * 2 ** 20
 
