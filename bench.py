@@ -105,28 +105,48 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
+class GpuRun:
+    """Timings of one single-solve leg: `elapsed` (s, host clock around the
+    timed steps), `region_ms` (ms per step from HIP events recorded on the
+    solver's stream before and after the timed steps: with one launch per
+    step, the average launch duration over the timed region), `stage_ms`
+    (mean per-kernel device time of separately timed single-step launches),
+    `diag`, and the ms per step of the repeat runs."""
+
+    def __init__(self, elapsed, region_ms, stage_ms, diag, rep_ms):
+        self.elapsed, self.region_ms, self.stage_ms = elapsed, region_ms, stage_ms
+        self.diag, self.rep_ms = diag, rep_ms
+
+
 def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0, repeats=None):
-    """Time `steps` RK4 steps after `warmup`, then the per-kernel device time
-    of `timed_stage_steps` single-step launches.  With repeats = (r, k), r
-    further timed runs of k steps each follow the timed steps, and their ms
-    per step come back as a fourth element."""
+    """Time `steps` RK4 steps after `warmup` on a stream of torch's (so HIP
+    events can bracket them on the stream the kernels run on), then the
+    per-kernel device time of `timed_stage_steps` single-step launches.  With
+    repeats = (r, k), r further timed runs of k steps each follow the timed
+    steps."""
     import numpy as np
     import torch
     from paper_1803_01291_amd import hb
 
     p0, p1 = w.initial()
-    h = hb.hb_create(hb.config_from_workload(w, precision, flags))
+    stream = torch.cuda.Stream()  # default priority
+    h = hb.hb_create(hb.config_from_workload(w, precision, flags, stream=stream.cuda_stream))
     rep_ms = []
     try:
         hb.hb_set_initial(h, p0, p1)
         hb.hb_step(h, warmup)
         hb.hb_sync(h)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record(stream)
         hb.hb_step(h, steps)
+        e1.record(stream)
         hb.hb_sync(h)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        region_ms = e0.elapsed_time(e1) / steps
         if repeats:
             r, k = repeats
             for _ in range(r):
@@ -138,9 +158,7 @@ def run_gpu(w, precision, steps, warmup, timed_stage_steps, flags=0, repeats=Non
         d = hb.hb_diagnostics(h, allow_nonfinite=True)
     finally:
         hb.hb_destroy(h)
-    if repeats:
-        return elapsed, [m / timed_stage_steps for m in stage_ms], d, rep_ms
-    return elapsed, [m / timed_stage_steps for m in stage_ms], d
+    return GpuRun(elapsed, region_ms, [m / timed_stage_steps for m in stage_ms], d, rep_ms)
 
 
 def run_batch(count, steps, warmup, tune_steps=3):
@@ -233,12 +251,13 @@ def run_shard(steps, warmup):
     stands in for the planes a neighbour would send."""
     import synth_inputs as si
     sw = si.slab_config(steps)
-    elapsed, stage_ms, _ = run_gpu(sw, 0, steps, warmup, 20)
+    g = run_gpu(sw, 0, steps, warmup, 20)
     return {"grid": [512, 512, 64], "steps": steps,
-            "pt_updates_per_s": sw.points * steps / elapsed,
-            "ms_per_step": elapsed / steps * 1e3, "kernel_ms": sum(stage_ms),
-            "GBps": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9,
-            "frac": STEP_BYTES[0] * sw.points / (sum(stage_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "pt_updates_per_s": sw.points * steps / g.elapsed,
+            "ms_per_step": g.elapsed / steps * 1e3, "kernel_ms": g.region_ms,
+            "kernel_ms_single": sum(g.stage_ms),
+            "GBps": STEP_BYTES[0] * sw.points / (g.region_ms * 1e-3) / 1e9,
+            "frac": STEP_BYTES[0] * sw.points / (g.region_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def run_precision_c3(steps):
@@ -312,12 +331,12 @@ def run_paper_grid(steps, warmup):
     w = si.example7_config(500, steps)
     out = {"grid": list(w.n), "dt": w.dt, "steps": steps, "paper_hours_to_t50": 27.0}
     for prec, name in ((0, "f64"), (1, "f32c")):
-        elapsed, stage_ms, d = run_gpu(w, prec, steps, warmup, 10)
-        ms = elapsed / steps * 1e3
-        out[name] = {"pt_updates_per_s": w.points * steps / elapsed, "ms_per_step": ms,
-                     "kernel_ms": sum(stage_ms),
+        g = run_gpu(w, prec, steps, warmup, 10)
+        ms = g.elapsed / steps * 1e3
+        out[name] = {"pt_updates_per_s": w.points * steps / g.elapsed, "ms_per_step": ms,
+                     "kernel_ms": g.region_ms, "kernel_ms_single": sum(g.stage_ms),
                      "projected_hours_to_t50": 5e5 * ms / 3.6e6,
-                     "nonfinite": d["nonfinite"]}
+                     "nonfinite": g.diag["nonfinite"]}
     return out
 
 
@@ -528,11 +547,15 @@ def main():
     N = w.points
     from paper_1803_01291_amd import hb as _hb
     flags = {"step": 0, "pairs": _hb.HB_PAIRWISE, "stages": _hb.HB_STAGEWISE}[args.scheme]
-    elapsed, stage_ms, diag, rep_ms = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps, flags,
-                                              repeats=(args.repeats, args.repeat_steps))
-    # the whole-step kernel is one launch per step; the comparison schemes'
-    # kernels are summed over the step
-    kernel_ms = sum(stage_ms)
+    g = run_gpu(w, 0, args.steps, args.warmup, args.stage_steps, flags,
+                repeats=(args.repeats, args.repeat_steps))
+    elapsed, diag, rep_ms = g.elapsed, g.diag, g.rep_ms
+    # the dominant kernel's average launch duration: HIP events on the
+    # solver's stream around the timed steps, one launch per step (the
+    # comparison schemes: their kernels summed over the step); the
+    # separately timed single launches are reported beside it
+    kernel_ms = g.region_ms
+    kernel_ms_single = sum(g.stage_ms)
     rate = N * args.steps / elapsed
     # algorithmic bytes per launch of the timed scheme: the whole-step kernel
     # reads and writes each point's 16-byte state slot once (32 B/point), the
@@ -572,7 +595,8 @@ def main():
                      "kernel": {"step": "step_kernel (whole RK4 step)",
                                 "pairs": "pair_kernel x 2 (sum per step)",
                                 "stages": "stage_kernel x 4 (sum per step)"}[args.scheme],
-                     "kernel_ms": kernel_ms,
+                     "kernel_ms": kernel_ms, "kernel_ms_timing": "HIP events around the timed steps",
+                     "kernel_ms_single": kernel_ms_single,
                      "bytes_per_point": own_b,
                      "contract_19pass_bytes_per_point": sum(STAGEWISE_BYTES[0]),
                      "contract_19pass_equiv_GBps": contract,
@@ -594,10 +618,10 @@ def main():
     }
     if not args.no_forms:
         progress("forms")
-        e32, ms32, _ = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
-        k32 = sum(ms32)
+        g32 = run_gpu(w, 1, args.steps, args.warmup, args.stage_steps, flags)
+        e32, k32 = g32.elapsed, g32.region_ms
         out["forms"] = {"f32c": {"value": N * args.steps / e32, "speedup_vs_f64": elapsed / e32,
-                                 "kernel_ms": k32,
+                                 "kernel_ms": k32, "kernel_ms_single": sum(g32.stage_ms),
                                  "GBps": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9,
                                  "frac": STEP_BYTES[1] * N / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                  "contract_19pass_equiv_GBps":
